@@ -1,0 +1,84 @@
+"""CPU oracle for FLIC range-image clustering (ctypes wrapper over flic_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg; the product package never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "flic_oracle.c")
+_LIB = os.path.join(_HERE, "libflic_oracle.so")
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared"]
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into oracle/libflic_oracle.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        fp = ctypes.POINTER(ctypes.c_float)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.flic_oracle_cluster.restype = ctypes.c_int32
+        L.flic_oracle_cluster.argtypes = [fp, ctypes.c_int32, ctypes.c_int32, fp, fp,
+                                          ctypes.c_float, ctypes.c_int32, ip]
+        L.flic_oracle_dist2.restype = ctypes.c_float
+        L.flic_oracle_dist2.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        _lib = L
+    return _lib
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def dist2(d1: float, d2: float, cos_alpha: float) -> np.float32:
+    """Eq. (4) in binary32."""
+    return np.float32(lib().flic_oracle_dist2(d1, d2, cos_alpha))
+
+
+def cluster_status(range_img: np.ndarray, cos_v: np.ndarray, cos_h: np.ndarray,
+                   threshold: float, skip_depth: int, H: Optional[int] = None,
+                   W: Optional[int] = None):
+    """Raw call: returns (status, labels)."""
+    r = np.ascontiguousarray(range_img, dtype=np.float32)
+    if H is None:
+        H, W = r.shape
+    cv = np.ascontiguousarray(cos_v, dtype=np.float32)
+    ch = np.ascontiguousarray(cos_h, dtype=np.float32)
+    out = np.full(max(H * W, 1), -7, dtype=np.int32)
+    st = lib().flic_oracle_cluster(_fptr(r), H, W, _fptr(cv), _fptr(ch),
+                                   float(threshold), int(skip_depth),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return st, out[: H * W].reshape(H, W) if H * W > 0 else out[:0]
+
+
+def cluster(range_img: np.ndarray, cos_v: np.ndarray, cos_h: np.ndarray,
+            threshold: float, skip_depth: int) -> np.ndarray:
+    """Labels int32 [H, W]: minimum linear index of each component, -1 if missing."""
+    st, out = cluster_status(range_img, cos_v, cos_h, threshold, skip_depth)
+    if st != 0:
+        raise ValueError(f"flic_oracle_cluster failed with status {st}")
+    return out
+
+
+def cluster_scan(scan) -> np.ndarray:
+    return cluster(scan.range_img, scan.cos_v, scan.cos_h, scan.threshold, scan.skip_depth)

@@ -1,0 +1,53 @@
+/*
+ * flic_oracle.h -- CPU oracle for FLIC range-image clustering.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
+ * correct statement of what the clustering computes; it exists so that tests
+ * and the benchmark's CPU baseline can check the GPU library against it.  No
+ * product code may link, load or call it, and it shares no code with the GPU
+ * path.
+ *
+ * Semantics (FLIC, Hasecke, Hahn, Kummert, arXiv 2003.00575):
+ *   - A pixel is a measurement iff its range is > 0 and finite (Section
+ *     III.A: zero marks a missing / removed value).
+ *   - Two pixels are connected when the squared Euclidean distance recovered
+ *     by the cosine law, Eq. (4) D^2 = d1*d1 + d2*d2 - (2 cos a) * d1 * d2,
+ *     is <= T^2 (Section III.B, one physical threshold T).
+ *   - Neighbours: the same column k rows down, or the same row k columns to
+ *     the right with 360-degree wrap, for k = 1..N (k = 1 is the direct
+ *     4-neighbourhood of Section III.B.1; k >= 2 are the map/skip connections
+ *     of Section III.B.2, taken densely).
+ *   - Output: each measurement gets the smallest linear index r*W + c of its
+ *     connected component; missing pixels get -1.
+ */
+#ifndef FLIC_ORACLE_H
+#define FLIC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Eq. (4) evaluated in IEEE binary32, each operation rounded to nearest-even:
+ *   (d1*d1 + d2*d2) - ((2*cos_alpha) * (d1*d2))                            */
+float flic_oracle_dist2(float d1, float d2, float cos_alpha);
+
+/* Cluster one range image.
+ *   range      host [H][W] row-major float32 metres
+ *   cos_v      host [N][H]; cos_v[(k-1)*H + r] = cos(angle rows r, r+k);
+ *              entries r >= H-k are never read
+ *   cos_h      host [N][W]; cos_h[(k-1)*W + c] = cos(angle cols c, (c+k)%W)
+ *   threshold  metres, finite and >= 0; the test is D^2 <= fl32(T*T)
+ *   skip_depth N, 1 <= N <= 8, 2N < W
+ *   labels_out host [H][W] int32, written only on success
+ * Returns 0 on success, -1 for invalid arguments, -2 when memory runs out. */
+int32_t flic_oracle_cluster(const float* range, int32_t H, int32_t W,
+                            const float* cos_v, const float* cos_h,
+                            float threshold, int32_t skip_depth,
+                            int32_t* labels_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
