@@ -1,0 +1,143 @@
+/*
+ * flic.h -- FLIC range-image clustering on AMD Instinct MI355X (gfx950).
+ *
+ * FLIC (Hasecke, Hahn, Kummert, "FLIC: Fast Lidar Image Clustering", arXiv
+ * 2003.00575) segments a Lidar range image into object instances:
+ *
+ *   1. Edge test (Section III.B, Eq. 3/4).  Two pixels are connected when
+ *        D^2 = (d1*d1 + d2*d2) - ((2*cos a) * (d1*d2)) <= T^2
+ *      in IEEE binary32, each operation rounded to nearest-even, no fused
+ *      multiply-add, T^2 = fl32(T*T), ordered compare (NaN never connects).
+ *      Neighbours are the same column k rows below and the same row k columns
+ *      to the right with 360-degree wrap, for k = 1..N: k = 1 is the direct
+ *      4-neighbourhood (Section III.B.1), k >= 2 the map / skip connections
+ *      of Section III.B.2 applied to every pixel.
+ *   2. Pixels whose range is not (> 0 and finite) are missing measurements
+ *      (Section III.A, zero = removed) and take part in no edge.
+ *   3. Connected-component labelling over those edges (Section III.B.1), with
+ *      canonical labels: every measurement gets the smallest linear index
+ *      r*W + c of its component; missing pixels get -1.  The result is unique,
+ *      so every entry point returns the same bits for the same input.
+ *
+ * Conventions for every entry point:
+ *   - Device pointers are HIP device addresses on the context's device.
+ *     The caller owns every buffer; the library never frees or keeps a
+ *     caller pointer beyond completion of the work it enqueued.
+ *   - range and labels_out must not overlap each other or the tables.
+ *   - Arguments are validated on the host before any HIP call; an invalid
+ *     argument returns FLIC_EINVAL and leaves labels_out untouched.
+ *   - Failed HIP runtime calls return FLIC_EHIP; flic_last_error() then gives
+ *     a message (thread-local, valid until the next call on the thread).
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef FLIC_H
+#define FLIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t flic_status;
+#define FLIC_OK 0
+#define FLIC_EINVAL (-1)  /* invalid argument, nothing enqueued              */
+#define FLIC_ENOMEM (-2)  /* allocation failed or HBM budget exceeded         */
+#define FLIC_EHIP (-3)    /* HIP runtime error, see flic_last_error()         */
+
+#define FLIC_MAX_SKIP 8
+
+/* Angle tables supplied by the caller (the sensor's channel and azimuth
+ * geometry, Section III.B: "provided by the manufacturer").  Device pointers.
+ *   cos_v: [N][H] float32; cos_v[(k-1)*H + r] = cos(angle between rows r and
+ *          r+k); entries with r >= H-k are never read.
+ *   cos_h: [N][W] float32; cos_h[(k-1)*W + c] = cos(angle between columns c
+ *          and (c+k) mod W).
+ * The values are used exactly as given (never recomputed).                  */
+typedef struct {
+    const float* cos_v;
+    const float* cos_h;
+} flic_alpha_tables;
+
+/* One scan of a batch.  All pointers are device pointers.
+ *   range_img  [H][W] float32 metres, row-major (row = channel, col = azimuth)
+ *   H >= 1, W > 2*skip_depth, H*W <= INT32_MAX
+ *   threshold  metres, finite, >= 0      skip_depth  N, 1..FLIC_MAX_SKIP
+ *   labels_out [H][W] int32, scan-local linear indices                    */
+typedef struct {
+    const float* range_img;
+    int32_t H;
+    int32_t W;
+    flic_alpha_tables tables;
+    float threshold;
+    int32_t skip_depth;
+    int32_t* labels_out;
+} flic_scan;
+
+typedef struct flic_ctx flic_ctx;
+typedef struct flic_plan flic_plan;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context itself allocates (descriptor tables, plans); 0 means no
+ * cap.  Returns FLIC_EINVAL for a null out-pointer or bad device.           */
+flic_status flic_ctx_create(flic_ctx** out, int device, size_t hbm_budget_bytes);
+
+/* Destroy a context after synchronising the device work it enqueued. Plans
+ * created from it must be destroyed first.  Null is a no-op.               */
+void flic_ctx_destroy(flic_ctx* ctx);
+
+/* Cluster one scan (all pointers device pointers, see flic_scan for the
+ * layout) and block until the labels are written.  Uses a per-thread default
+ * context on the current HIP device and the null stream.                   */
+flic_status flic_cluster(const float* range_img, int32_t H, int32_t W,
+                         const flic_alpha_tables* alpha_tables,
+                         float threshold, int32_t skip_depth,
+                         int32_t* labels_out);
+
+/* Stream-ordered form of flic_cluster: enqueues the work on `hip_stream`
+ * (a hipStream_t, or null for the null stream) and returns at once.  The
+ * table pointers are read on the host during the call; the device buffers
+ * must stay valid until the stream reaches the end of the work.             */
+flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img,
+                               int32_t H, int32_t W,
+                               const flic_alpha_tables* alpha_tables,
+                               float threshold, int32_t skip_depth,
+                               int32_t* labels_out, void* hip_stream);
+
+/* Cluster n independent scans of any shapes, thresholds and skip depths in
+ * one stream-ordered sequence of launches (no per-scan launches).  `scans`
+ * is a host array read during the call.  Each scan's labels are identical to
+ * what flic_cluster returns for it alone.  n == 0 is a no-op.               */
+flic_status flic_cluster_batched(flic_ctx* ctx, const flic_scan* scans,
+                                 int32_t n, void* hip_stream);
+
+/* Build a reusable plan for batches shaped like `scans` (same n, and per
+ * entry the same H, W and skip_depth): descriptors are laid out once on the
+ * device, tile shapes come from the autotune table, and the launch sequence
+ * is captured in a hipGraph.                                               */
+flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n,
+                             flic_plan** out);
+
+/* Launch a plan on `hip_stream` for `scans`, which must match the plan's
+ * shapes entry by entry (pointers and thresholds may differ: changed
+ * descriptors are uploaded before the graph launch).  FLIC_EINVAL on a
+ * shape mismatch.                                                          */
+flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
+                             void* hip_stream);
+
+/* Destroy a plan (synchronises its last launch).  Null is a no-op.         */
+void flic_plan_destroy(flic_plan* plan);
+
+/* Tile shape used for scans of width W and height H (columns x rows per
+ * workgroup tile).  Overrides the built-in table when set (> 0) via
+ * flic_set_tile_override; tile_w must be 64, 128 or 256.                    */
+flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w);
+
+/* Message for the last error on this thread ("" if none).                  */
+const char* flic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

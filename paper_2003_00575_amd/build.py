@@ -1,0 +1,50 @@
+"""Build libflic.so (HIP kernels for gfx950 + the C-ABI host code) in-tree.
+
+    python -m paper_2003_00575_amd.build
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libflic.so")
+SOURCES = [os.path.join(CSRC, "flic_kernels.hip"), os.path.join(CSRC, "flic_api.cpp")]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+# -ffp-contract=off: the edge test must be a chain of separately rounded
+# binary32 operations (no fused multiply-add), bit-identical to the CPU.
+# -packed-fp32-ops off: no v_pk_*_f32 instructions are generated.
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-ffp-contract=off", "-fno-fast-math",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-command-line-argument",
+    "-I", os.path.join(ROOT, "include"),
+]
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def device_asm(out_path: str) -> str:
+    """Write the gfx950 assembly of the kernels (for instruction checks)."""
+    cmd = [HIPCC, *[f for f in FLAGS if f not in ("-shared", "-fPIC")], "-S", "--cuda-device-only",
+           "-o", out_path, SOURCES[0]]
+    subprocess.check_call(cmd)
+    return out_path
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
+    sys.exit(0)

@@ -1,0 +1,461 @@
+// flic_api.cpp -- C ABI of the FLIC clustering library: argument checks,
+// contexts, batch descriptors, plans (hipGraph), error reporting.
+#include "../../include/flic.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "flic_internal.h"
+
+using flic::ScanDesc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+flic_status fail(flic_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+flic_status fail(flic_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            return fail(FLIC_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char* a0 = static_cast<const char*>(a);
+    const char* b0 = static_cast<const char*>(b);
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+// Host-side check of one scan's arguments; nothing touches the device.
+flic_status check_scan(const float* range, int32_t H, int32_t W, const flic_alpha_tables* t,
+                       float threshold, int32_t N, const int32_t* labels, int idx) {
+    if (!range || !labels || !t || !t->cos_v || !t->cos_h)
+        return fail(FLIC_EINVAL, "scan %d: null pointer", idx);
+    if (H < 1 || W < 1) return fail(FLIC_EINVAL, "scan %d: H=%d W=%d", idx, H, W);
+    if (N < 1 || N > FLIC_MAX_SKIP)
+        return fail(FLIC_EINVAL, "scan %d: skip_depth %d outside 1..%d", idx, N, FLIC_MAX_SKIP);
+    if (2 * N >= W) return fail(FLIC_EINVAL, "scan %d: need 2*skip_depth < W (N=%d W=%d)", idx, N, W);
+    if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX)
+        return fail(FLIC_EINVAL, "scan %d: H*W exceeds INT32_MAX", idx);
+    if (!(threshold >= 0.0f) || !std::isfinite(threshold))
+        return fail(FLIC_EINVAL, "scan %d: threshold must be finite and >= 0", idx);
+    const size_t px = (size_t)H * (size_t)W;
+    if (overlaps(range, px * 4, labels, px * 4))
+        return fail(FLIC_EINVAL, "scan %d: range_img and labels_out overlap", idx);
+    if (overlaps(t->cos_v, (size_t)N * H * 4, labels, px * 4) ||
+        overlaps(t->cos_h, (size_t)N * W * 4, labels, px * 4))
+        return fail(FLIC_EINVAL, "scan %d: a table overlaps labels_out", idx);
+    return FLIC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+
+struct flic_ctx {
+    int device = 0;
+    size_t budget = 0;          // 0 = unlimited
+    size_t used = 0;            // device bytes held by this context and its plans
+    int tile_override = 0;
+    // batched-call staging: a ring of (pinned host, device) descriptor buffers
+    static constexpr int kRing = 4;
+    struct Slot {
+        void* host = nullptr;
+        void* dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    } ring[kRing];
+    int next = 0;
+};
+
+struct flic_plan {
+    flic_ctx* ctx = nullptr;
+    int32_t n = 0;
+    std::vector<flic_scan> shapes;     // shapes as planned
+    struct Group {                     // scans sharing one tile width
+        int tile_w;
+        int n_tiles;
+        size_t desc_off;               // byte offset of ScanDesc[members] in the blob
+        std::vector<int> members;      // scan indices
+    };
+    std::vector<Group> groups;
+    size_t blob_bytes = 0;
+    char* host_blob = nullptr;         // pinned copy of the device descriptor blob
+    void* dev_mem = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool launched = false;
+};
+
+namespace {
+
+int choose_tile_w(const flic_ctx* ctx, int32_t H, int32_t W) {
+    if (ctx && ctx->tile_override > 0) return ctx->tile_override;
+    // Full-height strips where they fit: 64 columns x 128 rows.  Narrower
+    // images keep 64 columns; short images widen the tile so a tile still
+    // holds about kTilePx pixels.
+    if (H <= 32 && W >= 2048) return 256;
+    if (H <= 64 && W >= 1024) return 128;
+    return 64;
+}
+
+ScanDesc make_desc(const flic_scan& s, int tile_w, int32_t tile_begin) {
+    ScanDesc d{};
+    d.range = s.range_img;
+    d.labels = s.labels_out;
+    d.cos_v = s.tables.cos_v;
+    d.cos_h = s.tables.cos_h;
+    d.H = s.H;
+    d.W = s.W;
+    d.N = s.skip_depth;
+    d.t2 = s.threshold * s.threshold;      // binary32 product, as in Eq. (4)
+    d.tile_w = tile_w;
+    d.tile_h = flic::tile_h_for(tile_w);
+    d.tiles_x = (s.W + tile_w - 1) / tile_w;
+    d.tiles_y = (s.H + d.tile_h - 1) / d.tile_h;
+    d.tile_begin = tile_begin;
+    return d;
+}
+
+flic_status check_scans(const flic_scan* scans, int32_t n) {
+    if (n < 0) return fail(FLIC_EINVAL, "n < 0");
+    if (n > 0 && !scans) return fail(FLIC_EINVAL, "scans is null");
+    for (int32_t i = 0; i < n; ++i) {
+        const flic_scan& s = scans[i];
+        flic_status st = check_scan(s.range_img, s.H, s.W, &s.tables, s.threshold, s.skip_depth,
+                                    s.labels_out, i);
+        if (st != FLIC_OK) return st;
+    }
+    // no scan may write into another scan's buffers
+    for (int32_t i = 0; i < n; ++i) {
+        const size_t pi = (size_t)scans[i].H * scans[i].W * 4;
+        for (int32_t j = 0; j < n; ++j) {
+            if (i == j) continue;
+            const size_t pj = (size_t)scans[j].H * scans[j].W * 4;
+            if (overlaps(scans[i].labels_out, pi, scans[j].labels_out, pj) ||
+                overlaps(scans[i].labels_out, pi, scans[j].range_img, pj))
+                return fail(FLIC_EINVAL, "scan %d labels_out overlaps scan %d buffers", i, j);
+        }
+    }
+    return FLIC_OK;
+}
+
+// Lay out descriptors + block maps for a batch, grouped by tile width.
+// Output: one contiguous byte image `blob` with, per group, ScanDesc[m] then
+// int32 block_scan[n_tiles]; `groups` get offsets into it (device base added
+// later).
+struct Layout {
+    std::vector<char> blob;
+    struct G { int tile_w; int n_tiles; size_t desc_off; size_t map_off; std::vector<int> members; };
+    std::vector<G> groups;
+};
+
+void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, Layout& L) {
+    L.blob.clear();
+    L.groups.clear();
+    const int widths[4] = {32, 64, 128, 256};
+    for (int wi = 0; wi < 4; ++wi) {
+        Layout::G g{widths[wi], 0, 0, 0, {}};
+        for (int32_t i = 0; i < n; ++i)
+            if (choose_tile_w(ctx, scans[i].H, scans[i].W) == widths[wi]) g.members.push_back(i);
+        if (g.members.empty()) continue;
+        std::vector<ScanDesc> descs;
+        std::vector<int32_t> map;
+        int32_t tiles = 0;
+        for (size_t m = 0; m < g.members.size(); ++m) {
+            ScanDesc d = make_desc(scans[g.members[m]], g.tile_w, tiles);
+            const int32_t t = d.tiles_x * d.tiles_y;
+            for (int32_t k = 0; k < t; ++k) map.push_back((int32_t)m);
+            tiles += t;
+            descs.push_back(d);
+        }
+        g.n_tiles = tiles;
+        auto align = [&](size_t a) { L.blob.resize((L.blob.size() + a - 1) / a * a); };
+        align(256);
+        g.desc_off = L.blob.size();
+        L.blob.resize(L.blob.size() + descs.size() * sizeof(ScanDesc));
+        memcpy(L.blob.data() + g.desc_off, descs.data(), descs.size() * sizeof(ScanDesc));
+        align(256);
+        g.map_off = L.blob.size();
+        L.blob.resize(L.blob.size() + map.size() * sizeof(int32_t));
+        memcpy(L.blob.data() + g.map_off, map.data(), map.size() * sizeof(int32_t));
+        L.groups.push_back(std::move(g));
+    }
+}
+
+flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t stream) {
+    for (const auto& g : L.groups) {
+        flic::BatchRef ref{};
+        ref.descs = reinterpret_cast<const ScanDesc*>(dev_base + g.desc_off);
+        ref.block_scan = reinterpret_cast<const int32_t*>(dev_base + g.map_off);
+        HIP_TRY(flic::launch_cluster(ref, g.tile_w, g.n_tiles, stream));
+    }
+    return FLIC_OK;
+}
+
+hipError_t set_device(int dev) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    return cur == dev ? hipSuccess : hipSetDevice(dev);
+}
+
+std::mutex g_default_mu;
+flic_ctx* g_default_ctx[64] = {};
+
+}  // namespace
+
+extern "C" {
+
+const char* flic_last_error(void) { return g_last_error.c_str(); }
+
+flic_status flic_ctx_create(flic_ctx** out, int device, size_t hbm_budget_bytes) {
+    if (!out) return fail(FLIC_EINVAL, "out is null");
+    if (device < 0) return fail(FLIC_EINVAL, "device %d", device);
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device >= count) return fail(FLIC_EINVAL, "device %d of %d", device, count);
+    flic_ctx* c = new flic_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return FLIC_OK;
+}
+
+void flic_ctx_destroy(flic_ctx* ctx) {
+    if (!ctx) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
+    for (auto& s : ctx->ring) {
+        if (s.done) { (void)hipEventSynchronize(s.done); (void)hipEventDestroy(s.done); }
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.host) (void)hipHostFree(s.host);
+    }
+    (void)hipSetDevice(prev);
+    delete ctx;
+}
+
+flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    if (tile_w != 0 && tile_w != 32 && tile_w != 64 && tile_w != 128 && tile_w != 256)
+        return fail(FLIC_EINVAL, "tile_w %d not in {0, 32, 64, 128, 256}", tile_w);
+    ctx->tile_override = tile_w;
+    return FLIC_OK;
+}
+
+flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img, int32_t H, int32_t W,
+                               const flic_alpha_tables* alpha_tables, float threshold,
+                               int32_t skip_depth, int32_t* labels_out, void* hip_stream) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    flic_status st = check_scan(range_img, H, W, alpha_tables, threshold, skip_depth, labels_out, 0);
+    if (st != FLIC_OK) return st;
+    flic_scan s{range_img, H, W, *alpha_tables, threshold, skip_depth, labels_out};
+    const int tw = choose_tile_w(ctx, H, W);
+    flic::BatchRef ref{};
+    ref.one = make_desc(s, tw, 0);
+    HIP_TRY(set_device(ctx->device));
+    HIP_TRY(flic::launch_cluster(ref, tw, ref.one.tiles_x * ref.one.tiles_y,
+                                 static_cast<hipStream_t>(hip_stream)));
+    return FLIC_OK;
+}
+
+flic_status flic_cluster(const float* range_img, int32_t H, int32_t W,
+                         const flic_alpha_tables* alpha_tables, float threshold,
+                         int32_t skip_depth, int32_t* labels_out) {
+    flic_status st = check_scan(range_img, H, W, alpha_tables, threshold, skip_depth, labels_out, 0);
+    if (st != FLIC_OK) return st;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(FLIC_EINVAL, "device %d", dev);
+    flic_ctx* ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_default_mu);
+        if (!g_default_ctx[dev]) {
+            st = flic_ctx_create(&g_default_ctx[dev], dev, 0);
+            if (st != FLIC_OK) return st;
+        }
+        ctx = g_default_ctx[dev];
+    }
+    st = flic_cluster_async(ctx, range_img, H, W, alpha_tables, threshold, skip_depth, labels_out,
+                            nullptr);
+    if (st != FLIC_OK) return st;
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    return FLIC_OK;
+}
+
+flic_status flic_cluster_batched(flic_ctx* ctx, const flic_scan* scans, int32_t n,
+                                 void* hip_stream) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    flic_status st = check_scans(scans, n);
+    if (st != FLIC_OK) return st;
+    if (n == 0) return FLIC_OK;
+    Layout L;
+    build_layout(ctx, scans, n, L);
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(set_device(ctx->device));
+
+    flic_ctx::Slot& slot = ctx->ring[ctx->next];
+    ctx->next = (ctx->next + 1) % flic_ctx::kRing;
+    if (slot.pending) {
+        HIP_TRY(hipEventSynchronize(slot.done));    // previous user of this slot finished
+        slot.pending = false;
+    }
+    if (slot.cap < L.blob.size()) {
+        size_t cap = 4096;
+        while (cap < L.blob.size()) cap *= 2;
+        if (ctx->budget && ctx->used - slot.cap + cap > ctx->budget)
+            return fail(FLIC_ENOMEM, "descriptor buffer of %zu bytes exceeds the HBM budget", cap);
+        if (slot.dev) HIP_TRY(hipFree(slot.dev));
+        if (slot.host) HIP_TRY(hipHostFree(slot.host));
+        ctx->used -= slot.cap;
+        slot.dev = slot.host = nullptr;
+        slot.cap = 0;
+        if (hipMalloc(&slot.dev, cap) != hipSuccess)
+            return fail(FLIC_ENOMEM, "hipMalloc(%zu) failed", cap);
+        if (hipHostMalloc(&slot.host, cap, hipHostMallocDefault) != hipSuccess)
+            return fail(FLIC_ENOMEM, "hipHostMalloc(%zu) failed", cap);
+        slot.cap = cap;
+        ctx->used += cap;
+        if (!slot.done) HIP_TRY(hipEventCreateWithFlags(&slot.done, hipEventDisableTiming));
+    }
+    memcpy(slot.host, L.blob.data(), L.blob.size());
+    HIP_TRY(hipMemcpyAsync(slot.dev, slot.host, L.blob.size(), hipMemcpyHostToDevice, stream));
+    st = enqueue_layout(L, static_cast<const char*>(slot.dev), stream);
+    if (st != FLIC_OK) return st;
+    HIP_TRY(hipEventRecord(slot.done, stream));
+    slot.pending = true;
+    return FLIC_OK;
+}
+
+flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, flic_plan** out) {
+    if (!ctx || !out) return fail(FLIC_EINVAL, "null ctx or out");
+    if (n < 1) return fail(FLIC_EINVAL, "a plan needs n >= 1");
+    flic_status st = check_scans(scans, n);
+    if (st != FLIC_OK) return st;
+    Layout L;
+    build_layout(ctx, scans, n, L);
+    if (ctx->budget && ctx->used + L.blob.size() > ctx->budget)
+        return fail(FLIC_ENOMEM, "plan of %zu bytes exceeds the HBM budget", L.blob.size());
+    HIP_TRY(set_device(ctx->device));
+    flic_plan* p = new flic_plan();
+    p->ctx = ctx;
+    p->n = n;
+    p->shapes.assign(scans, scans + n);
+    p->blob_bytes = L.blob.size();
+    for (const auto& g : L.groups) p->groups.push_back({g.tile_w, g.n_tiles, g.desc_off, g.members});
+    auto cleanup = [&](flic_status s) {
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        if (p->done) (void)hipEventDestroy(p->done);
+        if (p->dev_mem) { (void)hipFree(p->dev_mem); ctx->used -= p->blob_bytes; }
+        if (p->host_blob) (void)hipHostFree(p->host_blob);
+        delete p;
+        return s;
+    };
+    if (hipMalloc(&p->dev_mem, p->blob_bytes) != hipSuccess) {
+        p->dev_mem = nullptr;
+        return cleanup(fail(FLIC_ENOMEM, "hipMalloc(%zu) failed", p->blob_bytes));
+    }
+    ctx->used += p->blob_bytes;
+    if (hipHostMalloc((void**)&p->host_blob, p->blob_bytes, hipHostMallocDefault) != hipSuccess) {
+        p->host_blob = nullptr;
+        return cleanup(fail(FLIC_ENOMEM, "hipHostMalloc(%zu) failed", p->blob_bytes));
+    }
+    memcpy(p->host_blob, L.blob.data(), p->blob_bytes);
+    if (hipMemcpy(p->dev_mem, p->host_blob, p->blob_bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(FLIC_EHIP, "descriptor upload failed"));
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(fail(FLIC_EHIP, "hipStreamCreate failed"));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        flic_status s2 = enqueue_layout(L, static_cast<const char*>(p->dev_mem), cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+        if (s2 != FLIC_OK) { (void)hipStreamDestroy(cs); return cleanup(s2); }
+        e = e2;
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return cleanup(fail(FLIC_EHIP, "graph capture failed: %s", hipGetErrorString(e)));
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return cleanup(fail(FLIC_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e)));
+    if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
+        return cleanup(fail(FLIC_EHIP, "hipEventCreate failed"));
+    *out = p;
+    return FLIC_OK;
+}
+
+flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n, void* hip_stream) {
+    if (!plan) return fail(FLIC_EINVAL, "plan is null");
+    if (n != plan->n) return fail(FLIC_EINVAL, "plan holds %d scans, got %d", plan->n, n);
+    flic_status st = check_scans(scans, n);
+    if (st != FLIC_OK) return st;
+    for (int32_t i = 0; i < n; ++i) {
+        const flic_scan& a = scans[i];
+        const flic_scan& b = plan->shapes[i];
+        if (a.H != b.H || a.W != b.W || a.skip_depth != b.skip_depth)
+            return fail(FLIC_EINVAL, "scan %d shape differs from the plan", i);
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(set_device(plan->ctx->device));
+    // Refresh the descriptors whose pointers or threshold changed.  The pinned
+    // staging copy is rewritten only after the previous launch (and with it
+    // the previous upload) has completed.
+    std::vector<std::pair<size_t, ScanDesc>> changed;
+    for (const auto& g : plan->groups) {
+        for (size_t m = 0; m < g.members.size(); ++m) {
+            const size_t off = g.desc_off + m * sizeof(ScanDesc);
+            ScanDesc old;
+            memcpy(&old, plan->host_blob + off, sizeof old);
+            ScanDesc nd = make_desc(scans[g.members[m]], g.tile_w, old.tile_begin);
+            if (memcmp(&nd, &old, sizeof nd) != 0) changed.push_back({off, nd});
+        }
+    }
+    if (!changed.empty()) {
+        if (plan->launched) HIP_TRY(hipEventSynchronize(plan->done));
+        for (const auto& c : changed) memcpy(plan->host_blob + c.first, &c.second, sizeof(ScanDesc));
+        HIP_TRY(hipMemcpyAsync(plan->dev_mem, plan->host_blob, plan->blob_bytes,
+                               hipMemcpyHostToDevice, stream));
+    }
+    HIP_TRY(hipGraphLaunch(plan->exec, stream));
+    HIP_TRY(hipEventRecord(plan->done, stream));
+    plan->launched = true;
+    return FLIC_OK;
+}
+
+void flic_plan_destroy(flic_plan* plan) {
+    if (!plan) return;
+    (void)set_device(plan->ctx->device);
+    if (plan->launched) (void)hipEventSynchronize(plan->done);
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->done) (void)hipEventDestroy(plan->done);
+    if (plan->dev_mem) (void)hipFree(plan->dev_mem);
+    if (plan->host_blob) (void)hipHostFree(plan->host_blob);
+    plan->ctx->used -= plan->blob_bytes;
+    delete plan;
+}
+
+}  // extern "C"

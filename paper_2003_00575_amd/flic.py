@@ -1,0 +1,293 @@
+"""Python binding of libflic.so (ctypes): argument marshalling only.
+
+Every step of the clustering runs in the library's HIP kernels; torch is used
+for device memory and streams.  If libflic.so is missing the import of this
+module still works, but every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflic.so")
+
+FLIC_OK = 0
+FLIC_EINVAL = -1
+FLIC_ENOMEM = -2
+FLIC_EHIP = -3
+MAX_SKIP = 8
+
+
+class FlicError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"flic status {status}: {message}")
+        self.status = status
+
+
+class _Tables(ctypes.Structure):
+    _fields_ = [("cos_v", ctypes.c_void_p), ("cos_h", ctypes.c_void_p)]
+
+
+class _Scan(ctypes.Structure):
+    _fields_ = [("range_img", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("tables", _Tables), ("threshold", ctypes.c_float),
+                ("skip_depth", ctypes.c_int32), ("labels_out", ctypes.c_void_p)]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libflic.so (torch first, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(
+            f"{LIB_PATH} is not built; run `python -m paper_2003_00575_amd.build`")
+    import torch  # noqa: F401  -- loads the HIP runtime the tensors live in
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+    L.flic_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t]
+    L.flic_ctx_create.restype = i32
+    L.flic_ctx_destroy.argtypes = [vp]
+    L.flic_ctx_destroy.restype = None
+    L.flic_cluster.argtypes = [vp, i32, i32, ctypes.POINTER(_Tables), f32, i32, vp]
+    L.flic_cluster.restype = i32
+    L.flic_cluster_async.argtypes = [vp, vp, i32, i32, ctypes.POINTER(_Tables), f32, i32, vp, vp]
+    L.flic_cluster_async.restype = i32
+    L.flic_cluster_batched.argtypes = [vp, ctypes.POINTER(_Scan), i32, vp]
+    L.flic_cluster_batched.restype = i32
+    L.flic_plan_create.argtypes = [vp, ctypes.POINTER(_Scan), i32, ctypes.POINTER(vp)]
+    L.flic_plan_create.restype = i32
+    L.flic_plan_launch.argtypes = [vp, ctypes.POINTER(_Scan), i32, vp]
+    L.flic_plan_launch.restype = i32
+    L.flic_plan_destroy.argtypes = [vp]
+    L.flic_plan_destroy.restype = None
+    L.flic_set_tile_override.argtypes = [vp, i32]
+    L.flic_set_tile_override.restype = i32
+    L.flic_last_error.argtypes = []
+    L.flic_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != FLIC_OK:
+        msg = lib().flic_last_error().decode(errors="replace")
+        raise FlicError(status, msg)
+
+
+def last_error() -> str:
+    return lib().flic_last_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------------------
+# Raw pointer level (ints are device addresses)
+# ---------------------------------------------------------------------------
+
+def cluster_raw(range_ptr: int, H: int, W: int, cos_v_ptr: int, cos_h_ptr: int,
+                threshold: float, skip_depth: int, labels_ptr: int) -> int:
+    """flic_cluster with raw device addresses; returns the status code."""
+    t = _Tables(cos_v_ptr, cos_h_ptr)
+    return lib().flic_cluster(range_ptr, H, W, ctypes.byref(t), threshold, skip_depth, labels_ptr)
+
+
+def cluster_async_raw(ctx: int, range_ptr: int, H: int, W: int, cos_v_ptr: int, cos_h_ptr: int,
+                      threshold: float, skip_depth: int, labels_ptr: int, stream: int) -> int:
+    t = _Tables(cos_v_ptr, cos_h_ptr)
+    return lib().flic_cluster_async(ctx, range_ptr, H, W, ctypes.byref(t), threshold,
+                                    skip_depth, labels_ptr, stream)
+
+
+def batched_raw(ctx: int, scans: Sequence[tuple], stream: int) -> int:
+    """scans: (range_ptr, H, W, cos_v_ptr, cos_h_ptr, threshold, N, labels_ptr)."""
+    arr = (_Scan * max(1, len(scans)))()
+    for i, (rp, H, W, cv, ch, T, N, lp) in enumerate(scans):
+        arr[i] = _Scan(rp, H, W, _Tables(cv, ch), T, N, lp)
+    return lib().flic_cluster_batched(ctx, arr, len(scans), stream)
+
+
+# ---------------------------------------------------------------------------
+# torch level
+# ---------------------------------------------------------------------------
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _check_tensor(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU device")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+@dataclasses.dataclass
+class DeviceScan:
+    """Device tensors of one scan: range [H, W] f32, cos_v [N, H] f32,
+    cos_h [N, W] f32, labels [H, W] int32 (output)."""
+    range_img: "object"
+    cos_v: "object"
+    cos_h: "object"
+    threshold: float
+    skip_depth: int
+    labels: "object" = None
+
+    def validate(self) -> None:
+        import torch
+        H, W = self.range_img.shape
+        N = self.skip_depth
+        _check_tensor(self.range_img, torch.float32, (H, W), "range_img")
+        _check_tensor(self.cos_v, torch.float32, (N, H), "cos_v")
+        _check_tensor(self.cos_h, torch.float32, (N, W), "cos_h")
+        if self.labels is None:
+            self.labels = torch.empty((H, W), dtype=torch.int32, device=self.range_img.device)
+        _check_tensor(self.labels, torch.int32, (H, W), "labels")
+
+    def to_c(self) -> _Scan:
+        H, W = self.range_img.shape
+        return _Scan(self.range_img.data_ptr(), H, W,
+                     _Tables(self.cos_v.data_ptr(), self.cos_h.data_ptr()),
+                     float(self.threshold), int(self.skip_depth), self.labels.data_ptr())
+
+
+class Context:
+    """A flic_ctx on one device (one host thread at a time)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().flic_ctx_create(ctypes.byref(h), int(device), int(hbm_budget_bytes)))
+        self.handle = h
+        self.device = device
+
+    def close(self) -> None:
+        if self.handle:
+            lib().flic_ctx_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tile_width(self, tile_w: int) -> None:
+        """0 restores the built-in choice."""
+        _check(lib().flic_set_tile_override(self.handle, int(tile_w)))
+
+    def cluster_async(self, scan: DeviceScan, stream=None):
+        scan.validate()
+        H, W = scan.range_img.shape
+        t = _Tables(scan.cos_v.data_ptr(), scan.cos_h.data_ptr())
+        _check(lib().flic_cluster_async(self.handle, scan.range_img.data_ptr(), H, W,
+                                        ctypes.byref(t), float(scan.threshold),
+                                        int(scan.skip_depth), scan.labels.data_ptr(),
+                                        _stream_handle(stream)))
+        return scan.labels
+
+    def cluster_batched(self, scans: Sequence[DeviceScan], stream=None):
+        for s in scans:
+            s.validate()
+        arr = (_Scan * max(1, len(scans)))()
+        for i, s in enumerate(scans):
+            arr[i] = s.to_c()
+        _check(lib().flic_cluster_batched(self.handle, arr, len(scans), _stream_handle(stream)))
+        return [s.labels for s in scans]
+
+    def plan(self, scans: Sequence[DeviceScan]) -> "Plan":
+        return Plan(self, scans)
+
+
+class Plan:
+    """A hipGraph-captured launch for a fixed list of scan shapes."""
+
+    def __init__(self, ctx: Context, scans: Sequence[DeviceScan]):
+        for s in scans:
+            s.validate()
+        self.ctx = ctx
+        self.n = len(scans)
+        arr = (_Scan * max(1, self.n))()
+        for i, s in enumerate(scans):
+            arr[i] = s.to_c()
+        h = ctypes.c_void_p()
+        _check(lib().flic_plan_create(ctx.handle, arr, self.n, ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, scans: Sequence[DeviceScan], stream=None):
+        arr = (_Scan * max(1, len(scans)))()
+        for i, s in enumerate(scans):
+            s.validate()
+            arr[i] = s.to_c()
+        _check(lib().flic_plan_launch(self.handle, arr, len(scans), _stream_handle(stream)))
+        return [s.labels for s in scans]
+
+    def close(self) -> None:
+        if self.handle:
+            lib().flic_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device: Optional[int] = None) -> Context:
+    import torch
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def cluster(range_img, cos_v, cos_h, threshold: float, skip_depth: int, out=None, stream=None):
+    """Labels int32 [H, W] of one scan, enqueued on `stream` (default: the
+    current torch stream).  Inputs are device tensors."""
+    s = DeviceScan(range_img, cos_v, cos_h, threshold, skip_depth, out)
+    return default_context(range_img.device.index).cluster_async(s, stream)
+
+
+def cluster_sync(range_img, cos_v, cos_h, threshold: float, skip_depth: int, out=None):
+    """flic_cluster: blocking call on the null stream."""
+    s = DeviceScan(range_img, cos_v, cos_h, threshold, skip_depth, out)
+    s.validate()
+    H, W = range_img.shape
+    _check(cluster_raw(range_img.data_ptr(), H, W, cos_v.data_ptr(), cos_h.data_ptr(),
+                       float(threshold), int(skip_depth), s.labels.data_ptr()))
+    return s.labels
+
+
+def cluster_batched(scans: Sequence[DeviceScan], stream=None):
+    if not scans:
+        return []
+    return default_context(scans[0].range_img.device.index).cluster_batched(scans, stream)
+
+
+def to_device(scan, device="cuda") -> DeviceScan:
+    """Copy a host scan (synth.Scan) to device tensors."""
+    import torch
+    d = DeviceScan(torch.from_numpy(scan.range_img).to(device),
+                   torch.from_numpy(scan.cos_v).to(device),
+                   torch.from_numpy(scan.cos_h).to(device),
+                   scan.threshold, scan.skip_depth)
+    d.validate()          # allocates the labels tensor
+    return d

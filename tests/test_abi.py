@@ -1,0 +1,72 @@
+"""C-ABI checks that run without a GPU: the library loads, exports every
+function include/flic.h declares, and rejects invalid arguments on the host
+before any HIP call (labels_out untouched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2003_00575_amd import flic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "flic.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(flic_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(flic.LIB_PATH):
+        from paper_2003_00575_amd import build
+        build.build()
+    return flic.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+# Fake, never-dereferenced addresses: validation must reject before any HIP call.
+R, LBL, CV, CH = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+
+
+@pytest.mark.parametrize("args, why", [
+    ((0, 4, 64, CV, CH, 0.5, 3, LBL), "null range"),
+    ((R, 4, 64, CV, CH, 0.5, 3, 0), "null labels"),
+    ((R, 4, 64, 0, CH, 0.5, 3, LBL), "null cos_v"),
+    ((R, 4, 64, CV, 0, 0.5, 3, LBL), "null cos_h"),
+    ((R, 0, 64, CV, CH, 0.5, 3, LBL), "H < 1"),
+    ((R, 4, 0, CV, CH, 0.5, 3, LBL), "W < 1"),
+    ((R, 4, 64, CV, CH, 0.5, 0, LBL), "N < 1"),
+    ((R, 4, 64, CV, CH, 0.5, 9, LBL), "N > 8"),
+    ((R, 4, 6, CV, CH, 0.5, 3, LBL), "2N >= W"),
+    ((R, 65536, 65536, CV, CH, 0.5, 3, LBL), "H*W > INT32_MAX"),
+    ((R, 4, 64, CV, CH, float("nan"), 3, LBL), "NaN threshold"),
+    ((R, 4, 64, CV, CH, float("inf"), 3, LBL), "inf threshold"),
+    ((R, 4, 64, CV, CH, -0.5, 3, LBL), "negative threshold"),
+    ((R, 4, 64, CV, CH, 0.5, 3, R + 64), "range/labels overlap"),
+    ((R, 4, 64, CV, CH, 0.5, 3, CV), "table/labels overlap"),
+])
+def test_flic_cluster_rejects_invalid_arguments(L, args, why):
+    assert flic.cluster_raw(*args) == flic.FLIC_EINVAL, why
+    assert flic.last_error() != ""
+
+
+def test_null_tables_struct_and_ctx(L):
+    assert L.flic_cluster(R, 4, 64, None, 0.5, 3, LBL) == flic.FLIC_EINVAL
+    assert flic.cluster_async_raw(None, R, 4, 64, CV, CH, 0.5, 3, LBL, 0) == flic.FLIC_EINVAL
+    assert flic.batched_raw(None, [], 0) == flic.FLIC_EINVAL
+    assert L.flic_ctx_create(None, 0, 0) == flic.FLIC_EINVAL
+    assert L.flic_ctx_create(ctypes.byref(ctypes.c_void_p()), -1, 0) == flic.FLIC_EINVAL
+    assert L.flic_plan_launch(None, None, 0, None) == flic.FLIC_EINVAL
+    assert L.flic_set_tile_override(None, 64) == flic.FLIC_EINVAL
+    L.flic_ctx_destroy(None)
+    L.flic_plan_destroy(None)
