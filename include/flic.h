@@ -129,10 +129,21 @@ flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
 /* Destroy a plan (synchronises its last launch).  Null is a no-op.         */
 void flic_plan_destroy(flic_plan* plan);
 
-/* Tile shape used for scans of width W and height H (columns x rows per
- * workgroup tile).  Overrides the built-in table when set (> 0) via
- * flic_set_tile_override; tile_w must be 64, 128 or 256.                    */
+/* Force the tile width (columns per workgroup tile; the tile then holds
+ * 8192 / tile_w rows) for every later launch on this context: tile_w is 32,
+ * 64, 128 or 256, or 0 to restore the built-in choice by scan shape.  Labels
+ * do not depend on it.  Plans keep the width they were created with.       */
 flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w);
+
+/* Per-pass timing for measurement.  While enabled, every launch enqueued by
+ * flic_cluster_async / flic_cluster_batched on this context records HIP
+ * events on its stream around each of its kernels (plans are not timed).
+ * flic_ctx_pass_times waits for those events, writes the summed durations
+ * in milliseconds of the three passes (tile labelling, border merge,
+ * relabel) to total_ms[0..2], the number of timed launches to *n_launches,
+ * and starts a new accumulation.                                           */
+flic_status flic_ctx_set_pass_timing(flic_ctx* ctx, int32_t enable);
+flic_status flic_ctx_pass_times(flic_ctx* ctx, float* total_ms, int32_t* n_launches);
 
 /* Message for the last error on this thread ("" if none).                  */
 const char* flic_last_error(void);

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -87,6 +88,10 @@ struct flic_ctx {
         bool pending = false;
     } ring[kRing];
     int next = 0;
+    // optional per-pass timing (events around each kernel of each launch)
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, flic::kPasses + 1>> timed;   // recorded, not yet read
+    std::vector<std::array<hipEvent_t, flic::kPasses + 1>> spare;   // recycled
 };
 
 struct flic_plan {
@@ -205,12 +210,18 @@ void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, Layout
     }
 }
 
-flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t stream) {
+hipEvent_t* timing_events(flic_ctx* ctx, hipError_t* err);
+
+flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t stream,
+                           flic_ctx* timing_ctx) {
     for (const auto& g : L.groups) {
         flic::BatchRef ref{};
         ref.descs = reinterpret_cast<const ScanDesc*>(dev_base + g.desc_off);
         ref.block_scan = reinterpret_cast<const int32_t*>(dev_base + g.map_off);
-        HIP_TRY(flic::launch_cluster(ref, g.tile_w, g.n_tiles, stream));
+        hipError_t e;
+        hipEvent_t* ev = timing_events(timing_ctx, &e);
+        HIP_TRY(e);
+        HIP_TRY(flic::launch_cluster(ref, g.tile_w, g.n_tiles, stream, ev));
     }
     return FLIC_OK;
 }
@@ -220,6 +231,22 @@ hipError_t set_device(int dev) {
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return e;
     return cur == dev ? hipSuccess : hipSetDevice(dev);
+}
+
+// Events for one timed launch (null when timing is off).
+hipEvent_t* timing_events(flic_ctx* ctx, hipError_t* err) {
+    *err = hipSuccess;
+    if (!ctx || !ctx->timing) return nullptr;
+    std::array<hipEvent_t, flic::kPasses + 1> ev{};
+    if (!ctx->spare.empty()) {
+        ev = ctx->spare.back();
+        ctx->spare.pop_back();
+    } else {
+        for (auto& e : ev)
+            if ((*err = hipEventCreate(&e)) != hipSuccess) return nullptr;
+    }
+    ctx->timed.push_back(ev);
+    return ctx->timed.back().data();
 }
 
 std::mutex g_default_mu;
@@ -249,6 +276,9 @@ void flic_ctx_destroy(flic_ctx* ctx) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
+    for (auto* v : {&ctx->timed, &ctx->spare})
+        for (auto& ev : *v)
+            for (auto e : ev) { (void)hipEventSynchronize(e); (void)hipEventDestroy(e); }
     for (auto& s : ctx->ring) {
         if (s.done) { (void)hipEventSynchronize(s.done); (void)hipEventDestroy(s.done); }
         if (s.dev) (void)hipFree(s.dev);
@@ -256,6 +286,29 @@ void flic_ctx_destroy(flic_ctx* ctx) {
     }
     (void)hipSetDevice(prev);
     delete ctx;
+}
+
+flic_status flic_ctx_set_pass_timing(flic_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    ctx->timing = enable != 0;
+    return FLIC_OK;
+}
+
+flic_status flic_ctx_pass_times(flic_ctx* ctx, float* total_ms, int32_t* n_launches) {
+    if (!ctx || !total_ms || !n_launches) return fail(FLIC_EINVAL, "null argument");
+    for (int i = 0; i < flic::kPasses; ++i) total_ms[i] = 0.0f;
+    *n_launches = (int32_t)ctx->timed.size();
+    for (auto& ev : ctx->timed) {
+        HIP_TRY(hipEventSynchronize(ev[flic::kPasses]));
+        for (int i = 0; i < flic::kPasses; ++i) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            total_ms[i] += ms;
+        }
+        ctx->spare.push_back(ev);
+    }
+    ctx->timed.clear();
+    return FLIC_OK;
 }
 
 flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w) {
@@ -277,8 +330,11 @@ flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img, int32_t H,
     flic::BatchRef ref{};
     ref.one = make_desc(s, tw, 0);
     HIP_TRY(set_device(ctx->device));
+    hipError_t e;
+    hipEvent_t* ev = timing_events(ctx, &e);
+    HIP_TRY(e);
     HIP_TRY(flic::launch_cluster(ref, tw, ref.one.tiles_x * ref.one.tiles_y,
-                                 static_cast<hipStream_t>(hip_stream)));
+                                 static_cast<hipStream_t>(hip_stream), ev));
     return FLIC_OK;
 }
 
@@ -343,7 +399,7 @@ flic_status flic_cluster_batched(flic_ctx* ctx, const flic_scan* scans, int32_t 
     }
     memcpy(slot.host, L.blob.data(), L.blob.size());
     HIP_TRY(hipMemcpyAsync(slot.dev, slot.host, L.blob.size(), hipMemcpyHostToDevice, stream));
-    st = enqueue_layout(L, static_cast<const char*>(slot.dev), stream);
+    st = enqueue_layout(L, static_cast<const char*>(slot.dev), stream, ctx);
     if (st != FLIC_OK) return st;
     HIP_TRY(hipEventRecord(slot.done, stream));
     slot.pending = true;
@@ -392,7 +448,7 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, f
         return cleanup(fail(FLIC_EHIP, "hipStreamCreate failed"));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        flic_status s2 = enqueue_layout(L, static_cast<const char*>(p->dev_mem), cs);
+        flic_status s2 = enqueue_layout(L, static_cast<const char*>(p->dev_mem), cs, nullptr);
         hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
         if (s2 != FLIC_OK) { (void)hipStreamDestroy(cs); return cleanup(s2); }
         e = e2;

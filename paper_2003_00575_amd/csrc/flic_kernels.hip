@@ -262,22 +262,28 @@ __global__ __launch_bounds__(kThreads) void k_relabel(BatchRef ref) {
 }
 
 template <int TW>
-hipError_t launch_tw(const BatchRef& ref, int n_tiles, hipStream_t stream) {
+hipError_t launch_tw(const BatchRef& ref, int n_tiles, hipStream_t stream, hipEvent_t* ev) {
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_label<TW>, dim3(n_tiles), dim3(kThreads), 0, stream, ref);
+    if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_border_merge<TW>, dim3(n_tiles), dim3(kThreads), 0, stream, ref);
+    if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_relabel<TW>, dim3(n_tiles), dim3(kThreads), 0, stream, ref);
+    if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_cluster(const BatchRef& ref, int tile_w, int n_tiles, hipStream_t stream) {
+hipError_t launch_cluster(const BatchRef& ref, int tile_w, int n_tiles, hipStream_t stream,
+                          hipEvent_t* events) {
     if (n_tiles <= 0) return hipSuccess;
     switch (tile_w) {
-        case 32: return launch_tw<32>(ref, n_tiles, stream);
-        case 64: return launch_tw<64>(ref, n_tiles, stream);
-        case 128: return launch_tw<128>(ref, n_tiles, stream);
-        case 256: return launch_tw<256>(ref, n_tiles, stream);
+        case 32: return launch_tw<32>(ref, n_tiles, stream, events);
+        case 64: return launch_tw<64>(ref, n_tiles, stream, events);
+        case 128: return launch_tw<128>(ref, n_tiles, stream, events);
+        case 256: return launch_tw<256>(ref, n_tiles, stream, events);
         default: return hipErrorInvalidValue;
     }
 }

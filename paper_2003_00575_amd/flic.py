@@ -69,6 +69,10 @@ def lib() -> ctypes.CDLL:
     L.flic_plan_destroy.restype = None
     L.flic_set_tile_override.argtypes = [vp, i32]
     L.flic_set_tile_override.restype = i32
+    L.flic_ctx_set_pass_timing.argtypes = [vp, i32]
+    L.flic_ctx_set_pass_timing.restype = i32
+    L.flic_ctx_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
+    L.flic_ctx_pass_times.restype = i32
     L.flic_last_error.argtypes = []
     L.flic_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -189,6 +193,17 @@ class Context:
         """0 restores the built-in choice."""
         _check(lib().flic_set_tile_override(self.handle, int(tile_w)))
 
+    def set_pass_timing(self, enable: bool) -> None:
+        _check(lib().flic_ctx_set_pass_timing(self.handle, int(bool(enable))))
+
+    def pass_times(self):
+        """(summed ms of [tile labelling, border merge, relabel], launches)
+        since the last call; waits for the timed work."""
+        arr = (ctypes.c_float * 3)()
+        n = ctypes.c_int32()
+        _check(lib().flic_ctx_pass_times(self.handle, arr, ctypes.byref(n)))
+        return [float(x) for x in arr], int(n.value)
+
     def cluster_async(self, scan: DeviceScan, stream=None):
         scan.validate()
         H, W = scan.range_img.shape
@@ -200,13 +215,23 @@ class Context:
         return scan.labels
 
     def cluster_batched(self, scans: Sequence[DeviceScan], stream=None):
+        arr = self.scan_array(scans)
+        _check(lib().flic_cluster_batched(self.handle, arr, len(scans), _stream_handle(stream)))
+        return [s.labels for s in scans]
+
+    @staticmethod
+    def scan_array(scans: Sequence[DeviceScan]):
+        """Marshalled flic_scan[] for repeated cluster_batched_array calls."""
         for s in scans:
             s.validate()
         arr = (_Scan * max(1, len(scans)))()
         for i, s in enumerate(scans):
             arr[i] = s.to_c()
-        _check(lib().flic_cluster_batched(self.handle, arr, len(scans), _stream_handle(stream)))
-        return [s.labels for s in scans]
+        arr._n = len(scans)
+        return arr
+
+    def cluster_batched_array(self, arr, stream=None) -> None:
+        _check(lib().flic_cluster_batched(self.handle, arr, arr._n, _stream_handle(stream)))
 
     def plan(self, scans: Sequence[DeviceScan]) -> "Plan":
         return Plan(self, scans)
@@ -226,6 +251,11 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib().flic_plan_create(ctx.handle, arr, self.n, ctypes.byref(h)))
         self.handle = h
+        self._arr = arr           # the planned scans, for relaunch()
+
+    def relaunch(self, stream=None) -> None:
+        """Launch again on the scans the plan was created with."""
+        _check(lib().flic_plan_launch(self.handle, self._arr, self.n, _stream_handle(stream)))
 
     def launch(self, scans: Sequence[DeviceScan], stream=None):
         arr = (_Scan * max(1, len(scans)))()
