@@ -130,8 +130,8 @@ flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
 void flic_plan_destroy(flic_plan* plan);
 
 /* Force the tile width (columns per workgroup tile; the tile then holds
- * 8192 / tile_w rows) for every later launch on this context: tile_w is 32,
- * 64, 128 or 256, or 0 to restore the built-in choice by scan shape.  Labels
+ * 8192 / tile_w rows) for every later launch on this context: tile_w is 64,
+ * 128 or 256, or 0 to restore the built-in choice by scan shape.  Labels
  * do not depend on it.  Plans keep the width they were created with.       */
 flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w);
 

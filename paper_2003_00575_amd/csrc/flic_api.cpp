@@ -98,8 +98,9 @@ struct flic_plan {
     flic_ctx* ctx = nullptr;
     int32_t n = 0;
     std::vector<flic_scan> shapes;     // shapes as planned
-    struct Group {                     // scans sharing one tile width
+    struct Group {                     // scans sharing one tile width and skip depth
         int tile_w;
+        int skip;
         int n_tiles;
         size_t desc_off;               // byte offset of ScanDesc[members] in the blob
         std::vector<int> members;      // scan indices
@@ -173,18 +174,19 @@ flic_status check_scans(const flic_scan* scans, int32_t n) {
 // later).
 struct Layout {
     std::vector<char> blob;
-    struct G { int tile_w; int n_tiles; size_t desc_off; size_t map_off; std::vector<int> members; };
+    struct G { int tile_w; int skip; int n_tiles; size_t desc_off; size_t map_off; std::vector<int> members; };
     std::vector<G> groups;
 };
 
 void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, Layout& L) {
     L.blob.clear();
     L.groups.clear();
-    const int widths[4] = {32, 64, 128, 256};
-    for (int wi = 0; wi < 4; ++wi) {
-        Layout::G g{widths[wi], 0, 0, 0, {}};
+    const int widths[3] = {64, 128, 256};
+    for (int gi = 0; gi < 3 * FLIC_MAX_SKIP; ++gi) {
+        Layout::G g{widths[gi / FLIC_MAX_SKIP], 1 + gi % FLIC_MAX_SKIP, 0, 0, 0, {}};
         for (int32_t i = 0; i < n; ++i)
-            if (choose_tile_w(ctx, scans[i].H, scans[i].W) == widths[wi]) g.members.push_back(i);
+            if (choose_tile_w(ctx, scans[i].H, scans[i].W) == g.tile_w && scans[i].skip_depth == g.skip)
+                g.members.push_back(i);
         if (g.members.empty()) continue;
         std::vector<ScanDesc> descs;
         std::vector<int32_t> map;
@@ -221,7 +223,7 @@ flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t st
         hipError_t e;
         hipEvent_t* ev = timing_events(timing_ctx, &e);
         HIP_TRY(e);
-        HIP_TRY(flic::launch_cluster(ref, g.tile_w, g.n_tiles, stream, ev));
+        HIP_TRY(flic::launch_cluster(ref, g.tile_w, g.skip, g.n_tiles, stream, ev));
     }
     return FLIC_OK;
 }
@@ -313,8 +315,8 @@ flic_status flic_ctx_pass_times(flic_ctx* ctx, float* total_ms, int32_t* n_launc
 
 flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w) {
     if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
-    if (tile_w != 0 && tile_w != 32 && tile_w != 64 && tile_w != 128 && tile_w != 256)
-        return fail(FLIC_EINVAL, "tile_w %d not in {0, 32, 64, 128, 256}", tile_w);
+    if (tile_w != 0 && tile_w != 64 && tile_w != 128 && tile_w != 256)
+        return fail(FLIC_EINVAL, "tile_w %d not in {0, 64, 128, 256}", tile_w);
     ctx->tile_override = tile_w;
     return FLIC_OK;
 }
@@ -333,7 +335,7 @@ flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img, int32_t H,
     hipError_t e;
     hipEvent_t* ev = timing_events(ctx, &e);
     HIP_TRY(e);
-    HIP_TRY(flic::launch_cluster(ref, tw, ref.one.tiles_x * ref.one.tiles_y,
+    HIP_TRY(flic::launch_cluster(ref, tw, skip_depth, ref.one.tiles_x * ref.one.tiles_y,
                                  static_cast<hipStream_t>(hip_stream), ev));
     return FLIC_OK;
 }
@@ -421,7 +423,7 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, f
     p->n = n;
     p->shapes.assign(scans, scans + n);
     p->blob_bytes = L.blob.size();
-    for (const auto& g : L.groups) p->groups.push_back({g.tile_w, g.n_tiles, g.desc_off, g.members});
+    for (const auto& g : L.groups) p->groups.push_back({g.tile_w, g.skip, g.n_tiles, g.desc_off, g.members});
     auto cleanup = [&](flic_status s) {
         if (p->exec) (void)hipGraphExecDestroy(p->exec);
         if (p->graph) (void)hipGraphDestroy(p->graph);

@@ -41,10 +41,10 @@ inline int tile_h_for(int tile_w) { return kTilePx / tile_w; }
 constexpr int kPasses = 3;
 
 // Enqueue the three passes (tile labelling, border merge, relabel) for
-// `n_tiles` tiles of width `tile_w` (32, 64, 128 or 256).  When `events` is
-// non-null, events[0] is recorded before the first pass and events[i + 1]
-// after pass i.
-hipError_t launch_cluster(const BatchRef& ref, int tile_w, int n_tiles, hipStream_t stream,
-                          hipEvent_t* events = nullptr);
+// `n_tiles` tiles of width `tile_w` (64, 128 or 256), all of skip depth
+// `skip` (1..kMaxSkip).  When `events` is non-null, events[0] is recorded
+// before the first pass and events[i + 1] after pass i.
+hipError_t launch_cluster(const BatchRef& ref, int tile_w, int skip, int n_tiles,
+                          hipStream_t stream, hipEvent_t* events = nullptr);
 
 }  // namespace flic
