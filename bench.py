@@ -50,6 +50,12 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-w", type=int, default=0, help="force a tile width (0 = built-in)")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="1: all launches on one stream; 3: one stream per threshold")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the timed batch and the per-kernel timing (for profilers)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 128 MiB device copy (reference for byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -96,12 +102,14 @@ def main() -> int:
     px_per_step = px_per_launch * launches_per_step
 
     seq = [0]
+    # one stream per threshold: the three launches of a step are independent
+    streams = [torch.cuda.Stream() for _ in THRESHOLDS] if args.streams > 1 else [stream] * 3
 
     def step_plan():
+        k = seq[0]
+        seq[0] += 1
         for ti in range(len(THRESHOLDS)):
-            j = seq[0]
-            seq[0] += 1
-            plans[(j % S, ti)].relaunch(stream)
+            plans[(k % S, ti)].relaunch(streams[ti])
 
     # ---- timed region: hipGraph plans ---------------------------------------
     for _ in range(args.warmup):
@@ -111,8 +119,14 @@ def main() -> int:
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     ev0.record(stream)
+    for st in streams:
+        st.wait_event(ev0)
     for _ in range(args.steps):
         step_plan()
+    for st in streams:
+        e = torch.cuda.Event()
+        e.record(st)
+        stream.wait_event(e)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -141,6 +155,19 @@ def main() -> int:
     achieved = alg_bytes / (avg[dom] * 1e-3) / 1e9
     print(f"[bench] passes (ms/launch): " + ", ".join(f"{n}={a:.4f}" for n, a in zip(names, avg)),
           file=sys.stderr, flush=True)
+
+    if args.profile_run:
+        if args.copy_calibration:
+            src = torch.empty(32 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "value": round(value, 3), "unit": "Gpix/s",
+                          "passes_ms_per_launch": {n: round(a, 5) for n, a in zip(names, avg)}}), flush=True)
+        for p in plans.values():
+            p.close()
+        return 0
 
     # ---- per-scan launches on the same batch ----------------------------------
     singles = {(s, ti): scans_for(s, ti) for s in range(S) for ti in range(len(THRESHOLDS))}
@@ -180,6 +207,13 @@ def main() -> int:
         lat_host.append((time.perf_counter() - t) * 1e3)
         lat_dev.append(a.elapsed_time(b))
 
+    if args.copy_calibration:
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
     # ---- CPU oracle on a bounded sample -------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -209,8 +243,9 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"large batch: {N_SCANS} scans x {H}x{W} f32 range images, "
-                               f"thresholds 0.3/0.5/1.0 m (3 launches per step), skip depth {SKIP}, "
-                               f"hipGraph plans, {S} rotating buffer sets",
+                               f"thresholds 0.3/0.5/1.0 m (3 launches per step, "
+                               f"{'one stream each' if args.streams > 1 else 'one stream'}), "
+                               f"skip depth {SKIP}, hipGraph plans, {S} rotating buffer sets",
                    "global_batch": N_SCANS * len(THRESHOLDS), "pixels_per_step": px_per_step,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

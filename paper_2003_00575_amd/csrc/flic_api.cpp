@@ -1,16 +1,18 @@
 // flic_api.cpp -- C ABI of the FLIC clustering library: argument checks,
-// contexts, batch descriptors, plans (hipGraph), error reporting.
+// contexts (descriptor + scratch ring), batch layout, plans (hipGraph),
+// pass timing and error reporting.
 #include "../../include/flic.h"
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <array>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "flic_internal.h"
@@ -67,84 +69,6 @@ flic_status check_scan(const float* range, int32_t H, int32_t W, const flic_alph
     return FLIC_OK;
 }
 
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// Context
-// ---------------------------------------------------------------------------
-
-struct flic_ctx {
-    int device = 0;
-    size_t budget = 0;          // 0 = unlimited
-    size_t used = 0;            // device bytes held by this context and its plans
-    int tile_override = 0;
-    // batched-call staging: a ring of (pinned host, device) descriptor buffers
-    static constexpr int kRing = 4;
-    struct Slot {
-        void* host = nullptr;
-        void* dev = nullptr;
-        size_t cap = 0;
-        hipEvent_t done = nullptr;
-        bool pending = false;
-    } ring[kRing];
-    int next = 0;
-    // optional per-pass timing (events around each kernel of each launch)
-    bool timing = false;
-    std::vector<std::array<hipEvent_t, flic::kPasses + 1>> timed;   // recorded, not yet read
-    std::vector<std::array<hipEvent_t, flic::kPasses + 1>> spare;   // recycled
-};
-
-struct flic_plan {
-    flic_ctx* ctx = nullptr;
-    int32_t n = 0;
-    std::vector<flic_scan> shapes;     // shapes as planned
-    struct Group {                     // scans sharing one tile width and skip depth
-        int tile_w;
-        int skip;
-        int n_tiles;
-        size_t desc_off;               // byte offset of ScanDesc[members] in the blob
-        std::vector<int> members;      // scan indices
-    };
-    std::vector<Group> groups;
-    size_t blob_bytes = 0;
-    char* host_blob = nullptr;         // pinned copy of the device descriptor blob
-    void* dev_mem = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipEvent_t done = nullptr;
-    bool launched = false;
-};
-
-namespace {
-
-int choose_tile_w(const flic_ctx* ctx, int32_t H, int32_t W) {
-    if (ctx && ctx->tile_override > 0) return ctx->tile_override;
-    // Full-height strips where they fit: 64 columns x 128 rows.  Narrower
-    // images keep 64 columns; short images widen the tile so a tile still
-    // holds about kTilePx pixels.
-    if (H <= 32 && W >= 2048) return 256;
-    if (H <= 64 && W >= 1024) return 128;
-    return 64;
-}
-
-ScanDesc make_desc(const flic_scan& s, int tile_w, int32_t tile_begin) {
-    ScanDesc d{};
-    d.range = s.range_img;
-    d.labels = s.labels_out;
-    d.cos_v = s.tables.cos_v;
-    d.cos_h = s.tables.cos_h;
-    d.H = s.H;
-    d.W = s.W;
-    d.N = s.skip_depth;
-    d.t2 = s.threshold * s.threshold;      // binary32 product, as in Eq. (4)
-    d.tile_w = tile_w;
-    d.tile_h = flic::tile_h_for(tile_w);
-    d.tiles_x = (s.W + tile_w - 1) / tile_w;
-    d.tiles_y = (s.H + d.tile_h - 1) / d.tile_h;
-    d.tile_begin = tile_begin;
-    return d;
-}
-
 flic_status check_scans(const flic_scan* scans, int32_t n) {
     if (n < 0) return fail(FLIC_EINVAL, "n < 0");
     if (n > 0 && !scans) return fail(FLIC_EINVAL, "scans is null");
@@ -168,19 +92,134 @@ flic_status check_scans(const flic_scan* scans, int32_t n) {
     return FLIC_OK;
 }
 
-// Lay out descriptors + block maps for a batch, grouped by tile width.
-// Output: one contiguous byte image `blob` with, per group, ScanDesc[m] then
-// int32 block_scan[n_tiles]; `groups` get offsets into it (device base added
-// later).
+hipError_t set_device(int dev) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    return cur == dev ? hipSuccess : hipSetDevice(dev);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context: a ring of launch slots.  Each slot owns a pinned + device copy of a
+// batch's descriptor blob and a device scratch buffer; a slot is reused only
+// after the event recorded behind its last launch has completed, so launches
+// in flight on any streams never share scratch.
+// ---------------------------------------------------------------------------
+
+struct flic_ctx {
+    int device = 0;
+    size_t budget = 0;          // 0 = unlimited
+    size_t used = 0;            // device bytes held by this context and its plans
+    int tile_override = 0;
+    static constexpr int kRing = 4;
+    struct Slot {
+        void* host = nullptr;   // pinned descriptor staging
+        void* dev = nullptr;    // device descriptors
+        size_t cap = 0;
+        void* scratch = nullptr;
+        size_t scratch_cap = 0;
+        hipEvent_t done = nullptr;
+        bool pending = false;
+    } ring[kRing];
+    int next = 0;
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, flic::kPasses + 1>> timed;   // recorded, not yet read
+    std::vector<std::array<hipEvent_t, flic::kPasses + 1>> spare;   // recycled
+};
+
+struct flic_plan {
+    flic_ctx* ctx = nullptr;
+    int32_t n = 0;
+    std::vector<flic_scan> shapes;     // shapes as planned
+    struct Group {                     // scans sharing one tile width and skip depth
+        int tile_w;
+        int skip;
+        int n_tiles;
+        size_t desc_off;               // byte offset of ScanDesc[members] in the blob
+        std::vector<int> members;      // scan indices
+    };
+    std::vector<Group> groups;
+    size_t blob_bytes = 0;
+    char* host_blob = nullptr;         // pinned copy of the device descriptor blob
+    void* dev_mem = nullptr;           // descriptors
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool launched = false;
+};
+
+namespace {
+
+int choose_tile_w(const flic_ctx* ctx, int32_t H, int32_t W) {
+    if (ctx && ctx->tile_override > 0) return ctx->tile_override;
+    // One tile row whenever the scan fits: 128 rows x 64 columns, 64 x 128
+    // or 32 x 256 (every tile holds kTilePx pixels).
+    if (H <= 32 && W >= 256) return 256;
+    if (H <= 64 && W >= 128) return 128;
+    return 64;
+}
+
+ScanDesc make_desc(const flic_scan& s, int tile_w, int32_t tile_begin, char* scratch) {
+    ScanDesc d{};
+    d.range = s.range_img;
+    d.labels = s.labels_out;
+    d.cos_v = s.tables.cos_v;
+    d.cos_h = s.tables.cos_h;
+    d.H = s.H;
+    d.W = s.W;
+    d.N = s.skip_depth;
+    d.t2 = s.threshold * s.threshold;      // binary32 product, as in Eq. (4)
+    d.tile_w = tile_w;
+    d.tile_h = flic::tile_h_for(tile_w);
+    d.tiles_x = (s.W + tile_w - 1) / tile_w;
+    d.tiles_y = (s.H + d.tile_h - 1) / d.tile_h;
+    d.chunks_per_row = (s.W + 63) / 64;
+    d.tile_begin = tile_begin;
+    const flic::ScratchLayout S = flic::scratch_layout(s.H, s.W, s.skip_depth, tile_w);
+    d.masks = reinterpret_cast<ulonglong2*>(scratch + S.masks);
+    d.parent = reinterpret_cast<int32_t*>(scratch + S.parent);
+    d.bcol_v = reinterpret_cast<float*>(scratch + S.bcol_v);
+    d.bcol_r = reinterpret_cast<int32_t*>(scratch + S.bcol_r);
+    d.brow_v = reinterpret_cast<float*>(scratch + S.brow_v);
+    d.brow_r = reinterpret_cast<int32_t*>(scratch + S.brow_r);
+    return d;
+}
+
+size_t scratch_bytes(const flic_ctx* ctx, const flic_scan* scans, int32_t n) {
+    size_t total = 0;
+    for (int32_t i = 0; i < n; ++i)
+        total += flic::scratch_layout(scans[i].H, scans[i].W, scans[i].skip_depth,
+                                      choose_tile_w(ctx, scans[i].H, scans[i].W)).total;
+    return total;
+}
+
+// Descriptors + block maps for a batch, grouped by (tile width, skip depth),
+// as one byte image: per group ScanDesc[members] then int32 block_scan[tiles].
+// Scans take consecutive scratch regions starting at `scratch`.
 struct Layout {
     std::vector<char> blob;
-    struct G { int tile_w; int skip; int n_tiles; size_t desc_off; size_t map_off; std::vector<int> members; };
+    struct G {
+        int tile_w, skip, n_tiles;
+        size_t desc_off, map_off;
+        std::vector<int> members;
+    };
     std::vector<G> groups;
 };
 
-void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, Layout& L) {
+void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, char* scratch, Layout& L) {
     L.blob.clear();
     L.groups.clear();
+    std::vector<char*> base(n);
+    size_t off = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        base[i] = scratch + off;
+        off += flic::scratch_layout(scans[i].H, scans[i].W, scans[i].skip_depth,
+                                    choose_tile_w(ctx, scans[i].H, scans[i].W)).total;
+    }
     const int widths[3] = {64, 128, 256};
     for (int gi = 0; gi < 3 * FLIC_MAX_SKIP; ++gi) {
         Layout::G g{widths[gi / FLIC_MAX_SKIP], 1 + gi % FLIC_MAX_SKIP, 0, 0, 0, {}};
@@ -192,7 +231,8 @@ void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, Layout
         std::vector<int32_t> map;
         int32_t tiles = 0;
         for (size_t m = 0; m < g.members.size(); ++m) {
-            ScanDesc d = make_desc(scans[g.members[m]], g.tile_w, tiles);
+            const int i = g.members[m];
+            ScanDesc d = make_desc(scans[i], g.tile_w, tiles, base[i]);
             const int32_t t = d.tiles_x * d.tiles_y;
             for (int32_t k = 0; k < t; ++k) map.push_back((int32_t)m);
             tiles += t;
@@ -212,29 +252,6 @@ void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, Layout
     }
 }
 
-hipEvent_t* timing_events(flic_ctx* ctx, hipError_t* err);
-
-flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t stream,
-                           flic_ctx* timing_ctx) {
-    for (const auto& g : L.groups) {
-        flic::BatchRef ref{};
-        ref.descs = reinterpret_cast<const ScanDesc*>(dev_base + g.desc_off);
-        ref.block_scan = reinterpret_cast<const int32_t*>(dev_base + g.map_off);
-        hipError_t e;
-        hipEvent_t* ev = timing_events(timing_ctx, &e);
-        HIP_TRY(e);
-        HIP_TRY(flic::launch_cluster(ref, g.tile_w, g.skip, g.n_tiles, stream, ev));
-    }
-    return FLIC_OK;
-}
-
-hipError_t set_device(int dev) {
-    int cur = -1;
-    hipError_t e = hipGetDevice(&cur);
-    if (e != hipSuccess) return e;
-    return cur == dev ? hipSuccess : hipSetDevice(dev);
-}
-
 // Events for one timed launch (null when timing is off).
 hipEvent_t* timing_events(flic_ctx* ctx, hipError_t* err) {
     *err = hipSuccess;
@@ -249,6 +266,72 @@ hipEvent_t* timing_events(flic_ctx* ctx, hipError_t* err) {
     }
     ctx->timed.push_back(ev);
     return ctx->timed.back().data();
+}
+
+flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t stream,
+                           flic_ctx* timing_ctx) {
+    for (const auto& g : L.groups) {
+        flic::BatchRef ref{};
+        ref.descs = reinterpret_cast<const ScanDesc*>(dev_base + g.desc_off);
+        ref.block_scan = reinterpret_cast<const int32_t*>(dev_base + g.map_off);
+        hipError_t e;
+        hipEvent_t* ev = timing_events(timing_ctx, &e);
+        HIP_TRY(e);
+        HIP_TRY(flic::launch_cluster(ref, g.tile_w, g.skip, g.n_tiles, (int)g.members.size(),
+                                     stream, ev));
+    }
+    return FLIC_OK;
+}
+
+size_t round_cap(size_t need) {
+    size_t cap = 4096;
+    while (cap < need) cap *= 2;
+    return cap;
+}
+
+// Next ring slot with at least `desc_bytes` of descriptors and
+// `scratch_need` of scratch, after its previous launch has finished.
+flic_status acquire_slot(flic_ctx* ctx, size_t desc_bytes, size_t scratch_need, flic_ctx::Slot** out) {
+    flic_ctx::Slot& slot = ctx->ring[ctx->next];
+    ctx->next = (ctx->next + 1) % flic_ctx::kRing;
+    if (slot.pending) {
+        HIP_TRY(hipEventSynchronize(slot.done));
+        slot.pending = false;
+    }
+    if (!slot.done) HIP_TRY(hipEventCreateWithFlags(&slot.done, hipEventDisableTiming));
+    if (desc_bytes > slot.cap) {
+        const size_t cap = round_cap(desc_bytes);
+        if (ctx->budget && ctx->used - slot.cap + cap > ctx->budget)
+            return fail(FLIC_ENOMEM, "descriptor buffer of %zu bytes exceeds the HBM budget", cap);
+        if (slot.dev) HIP_TRY(hipFree(slot.dev));
+        if (slot.host) HIP_TRY(hipHostFree(slot.host));
+        ctx->used -= slot.cap;
+        slot.dev = slot.host = nullptr;
+        slot.cap = 0;
+        if (hipMalloc(&slot.dev, cap) != hipSuccess) return fail(FLIC_ENOMEM, "hipMalloc(%zu) failed", cap);
+        if (hipHostMalloc(&slot.host, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipFree(slot.dev);
+            slot.dev = nullptr;
+            return fail(FLIC_ENOMEM, "hipHostMalloc(%zu) failed", cap);
+        }
+        slot.cap = cap;
+        ctx->used += cap;
+    }
+    if (scratch_need > slot.scratch_cap) {
+        const size_t cap = round_cap(scratch_need);
+        if (ctx->budget && ctx->used - slot.scratch_cap + cap > ctx->budget)
+            return fail(FLIC_ENOMEM, "scratch of %zu bytes exceeds the HBM budget", cap);
+        if (slot.scratch) HIP_TRY(hipFree(slot.scratch));
+        ctx->used -= slot.scratch_cap;
+        slot.scratch = nullptr;
+        slot.scratch_cap = 0;
+        if (hipMalloc(&slot.scratch, cap) != hipSuccess)
+            return fail(FLIC_ENOMEM, "hipMalloc(%zu) for scratch failed", cap);
+        slot.scratch_cap = cap;
+        ctx->used += cap;
+    }
+    *out = &slot;
+    return FLIC_OK;
 }
 
 std::mutex g_default_mu;
@@ -285,9 +368,18 @@ void flic_ctx_destroy(flic_ctx* ctx) {
         if (s.done) { (void)hipEventSynchronize(s.done); (void)hipEventDestroy(s.done); }
         if (s.dev) (void)hipFree(s.dev);
         if (s.host) (void)hipHostFree(s.host);
+        if (s.scratch) (void)hipFree(s.scratch);
     }
     (void)hipSetDevice(prev);
     delete ctx;
+}
+
+flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    if (tile_w != 0 && tile_w != 64 && tile_w != 128 && tile_w != 256)
+        return fail(FLIC_EINVAL, "tile_w %d not in {0, 64, 128, 256}", tile_w);
+    ctx->tile_override = tile_w;
+    return FLIC_OK;
 }
 
 flic_status flic_ctx_set_pass_timing(flic_ctx* ctx, int32_t enable) {
@@ -313,30 +405,27 @@ flic_status flic_ctx_pass_times(flic_ctx* ctx, float* total_ms, int32_t* n_launc
     return FLIC_OK;
 }
 
-flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w) {
-    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
-    if (tile_w != 0 && tile_w != 64 && tile_w != 128 && tile_w != 256)
-        return fail(FLIC_EINVAL, "tile_w %d not in {0, 64, 128, 256}", tile_w);
-    ctx->tile_override = tile_w;
-    return FLIC_OK;
-}
-
 flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img, int32_t H, int32_t W,
                                const flic_alpha_tables* alpha_tables, float threshold,
                                int32_t skip_depth, int32_t* labels_out, void* hip_stream) {
     if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
     flic_status st = check_scan(range_img, H, W, alpha_tables, threshold, skip_depth, labels_out, 0);
     if (st != FLIC_OK) return st;
-    flic_scan s{range_img, H, W, *alpha_tables, threshold, skip_depth, labels_out};
+    const flic_scan s{range_img, H, W, *alpha_tables, threshold, skip_depth, labels_out};
     const int tw = choose_tile_w(ctx, H, W);
-    flic::BatchRef ref{};
-    ref.one = make_desc(s, tw, 0);
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(set_device(ctx->device));
+    flic_ctx::Slot* slot = nullptr;
+    st = acquire_slot(ctx, 0, flic::scratch_layout(H, W, skip_depth, tw).total, &slot);
+    if (st != FLIC_OK) return st;
+    flic::BatchRef ref{};
+    ref.one = make_desc(s, tw, 0, static_cast<char*>(slot->scratch));
     hipError_t e;
     hipEvent_t* ev = timing_events(ctx, &e);
     HIP_TRY(e);
-    HIP_TRY(flic::launch_cluster(ref, tw, skip_depth, ref.one.tiles_x * ref.one.tiles_y,
-                                 static_cast<hipStream_t>(hip_stream), ev));
+    HIP_TRY(flic::launch_cluster(ref, tw, skip_depth, ref.one.tiles_x * ref.one.tiles_y, 1, stream, ev));
+    HIP_TRY(hipEventRecord(slot->done, stream));
+    slot->pending = true;
     return FLIC_OK;
 }
 
@@ -348,17 +437,13 @@ flic_status flic_cluster(const float* range_img, int32_t H, int32_t W,
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(FLIC_EINVAL, "device %d", dev);
-    flic_ctx* ctx;
-    {
-        std::lock_guard<std::mutex> lk(g_default_mu);
-        if (!g_default_ctx[dev]) {
-            st = flic_ctx_create(&g_default_ctx[dev], dev, 0);
-            if (st != FLIC_OK) return st;
-        }
-        ctx = g_default_ctx[dev];
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    if (!g_default_ctx[dev]) {
+        st = flic_ctx_create(&g_default_ctx[dev], dev, 0);
+        if (st != FLIC_OK) return st;
     }
-    st = flic_cluster_async(ctx, range_img, H, W, alpha_tables, threshold, skip_depth, labels_out,
-                            nullptr);
+    st = flic_cluster_async(g_default_ctx[dev], range_img, H, W, alpha_tables, threshold,
+                            skip_depth, labels_out, nullptr);
     if (st != FLIC_OK) return st;
     HIP_TRY(hipStreamSynchronize(nullptr));
     return FLIC_OK;
@@ -370,41 +455,21 @@ flic_status flic_cluster_batched(flic_ctx* ctx, const flic_scan* scans, int32_t 
     flic_status st = check_scans(scans, n);
     if (st != FLIC_OK) return st;
     if (n == 0) return FLIC_OK;
-    Layout L;
-    build_layout(ctx, scans, n, L);
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(set_device(ctx->device));
-
-    flic_ctx::Slot& slot = ctx->ring[ctx->next];
-    ctx->next = (ctx->next + 1) % flic_ctx::kRing;
-    if (slot.pending) {
-        HIP_TRY(hipEventSynchronize(slot.done));    // previous user of this slot finished
-        slot.pending = false;
-    }
-    if (slot.cap < L.blob.size()) {
-        size_t cap = 4096;
-        while (cap < L.blob.size()) cap *= 2;
-        if (ctx->budget && ctx->used - slot.cap + cap > ctx->budget)
-            return fail(FLIC_ENOMEM, "descriptor buffer of %zu bytes exceeds the HBM budget", cap);
-        if (slot.dev) HIP_TRY(hipFree(slot.dev));
-        if (slot.host) HIP_TRY(hipHostFree(slot.host));
-        ctx->used -= slot.cap;
-        slot.dev = slot.host = nullptr;
-        slot.cap = 0;
-        if (hipMalloc(&slot.dev, cap) != hipSuccess)
-            return fail(FLIC_ENOMEM, "hipMalloc(%zu) failed", cap);
-        if (hipHostMalloc(&slot.host, cap, hipHostMallocDefault) != hipSuccess)
-            return fail(FLIC_ENOMEM, "hipHostMalloc(%zu) failed", cap);
-        slot.cap = cap;
-        ctx->used += cap;
-        if (!slot.done) HIP_TRY(hipEventCreateWithFlags(&slot.done, hipEventDisableTiming));
-    }
-    memcpy(slot.host, L.blob.data(), L.blob.size());
-    HIP_TRY(hipMemcpyAsync(slot.dev, slot.host, L.blob.size(), hipMemcpyHostToDevice, stream));
-    st = enqueue_layout(L, static_cast<const char*>(slot.dev), stream, ctx);
+    // sizes first (the blob size does not depend on the scratch address)
+    Layout L;
+    build_layout(ctx, scans, n, nullptr, L);
+    flic_ctx::Slot* slot = nullptr;
+    st = acquire_slot(ctx, L.blob.size(), scratch_bytes(ctx, scans, n), &slot);
     if (st != FLIC_OK) return st;
-    HIP_TRY(hipEventRecord(slot.done, stream));
-    slot.pending = true;
+    build_layout(ctx, scans, n, static_cast<char*>(slot->scratch), L);
+    memcpy(slot->host, L.blob.data(), L.blob.size());
+    HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, L.blob.size(), hipMemcpyHostToDevice, stream));
+    st = enqueue_layout(L, static_cast<const char*>(slot->dev), stream, ctx);
+    if (st != FLIC_OK) return st;
+    HIP_TRY(hipEventRecord(slot->done, stream));
+    slot->pending = true;
     return FLIC_OK;
 }
 
@@ -414,25 +479,34 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, f
     flic_status st = check_scans(scans, n);
     if (st != FLIC_OK) return st;
     Layout L;
-    build_layout(ctx, scans, n, L);
-    if (ctx->budget && ctx->used + L.blob.size() > ctx->budget)
-        return fail(FLIC_ENOMEM, "plan of %zu bytes exceeds the HBM budget", L.blob.size());
+    build_layout(ctx, scans, n, nullptr, L);
+    const size_t scratch = scratch_bytes(ctx, scans, n);
+    if (ctx->budget && ctx->used + L.blob.size() + scratch > ctx->budget)
+        return fail(FLIC_ENOMEM, "plan of %zu bytes exceeds the HBM budget", L.blob.size() + scratch);
     HIP_TRY(set_device(ctx->device));
     flic_plan* p = new flic_plan();
     p->ctx = ctx;
     p->n = n;
     p->shapes.assign(scans, scans + n);
-    p->blob_bytes = L.blob.size();
-    for (const auto& g : L.groups) p->groups.push_back({g.tile_w, g.skip, g.n_tiles, g.desc_off, g.members});
     auto cleanup = [&](flic_status s) {
         if (p->exec) (void)hipGraphExecDestroy(p->exec);
         if (p->graph) (void)hipGraphDestroy(p->graph);
         if (p->done) (void)hipEventDestroy(p->done);
         if (p->dev_mem) { (void)hipFree(p->dev_mem); ctx->used -= p->blob_bytes; }
+        if (p->scratch) { (void)hipFree(p->scratch); ctx->used -= p->scratch_bytes; }
         if (p->host_blob) (void)hipHostFree(p->host_blob);
         delete p;
         return s;
     };
+    if (hipMalloc(&p->scratch, scratch) != hipSuccess) {
+        p->scratch = nullptr;
+        return cleanup(fail(FLIC_ENOMEM, "hipMalloc(%zu) for scratch failed", scratch));
+    }
+    p->scratch_bytes = scratch;
+    ctx->used += scratch;
+    build_layout(ctx, scans, n, static_cast<char*>(p->scratch), L);
+    p->blob_bytes = L.blob.size();
+    for (const auto& g : L.groups) p->groups.push_back({g.tile_w, g.skip, g.n_tiles, g.desc_off, g.members});
     if (hipMalloc(&p->dev_mem, p->blob_bytes) != hipSuccess) {
         p->dev_mem = nullptr;
         return cleanup(fail(FLIC_ENOMEM, "hipMalloc(%zu) failed", p->blob_bytes));
@@ -478,16 +552,22 @@ flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
     }
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(set_device(plan->ctx->device));
-    // Refresh the descriptors whose pointers or threshold changed.  The pinned
-    // staging copy is rewritten only after the previous launch (and with it
-    // the previous upload) has completed.
+    // Refresh descriptors whose pointers or threshold changed (scratch stays
+    // the plan's own).  The pinned staging copy is rewritten only after the
+    // previous launch, and with it the previous upload, has completed.
     std::vector<std::pair<size_t, ScanDesc>> changed;
     for (const auto& g : plan->groups) {
         for (size_t m = 0; m < g.members.size(); ++m) {
             const size_t off = g.desc_off + m * sizeof(ScanDesc);
             ScanDesc old;
             memcpy(&old, plan->host_blob + off, sizeof old);
-            ScanDesc nd = make_desc(scans[g.members[m]], g.tile_w, old.tile_begin);
+            ScanDesc nd = old;
+            const flic_scan& s = scans[g.members[m]];
+            nd.range = s.range_img;
+            nd.labels = s.labels_out;
+            nd.cos_v = s.tables.cos_v;
+            nd.cos_h = s.tables.cos_h;
+            nd.t2 = s.threshold * s.threshold;
             if (memcmp(&nd, &old, sizeof nd) != 0) changed.push_back({off, nd});
         }
     }
@@ -496,6 +576,7 @@ flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
         for (const auto& c : changed) memcpy(plan->host_blob + c.first, &c.second, sizeof(ScanDesc));
         HIP_TRY(hipMemcpyAsync(plan->dev_mem, plan->host_blob, plan->blob_bytes,
                                hipMemcpyHostToDevice, stream));
+        plan->shapes.assign(scans, scans + n);
     }
     HIP_TRY(hipGraphLaunch(plan->exec, stream));
     HIP_TRY(hipEventRecord(plan->done, stream));
@@ -511,8 +592,9 @@ void flic_plan_destroy(flic_plan* plan) {
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->done) (void)hipEventDestroy(plan->done);
     if (plan->dev_mem) (void)hipFree(plan->dev_mem);
+    if (plan->scratch) (void)hipFree(plan->scratch);
     if (plan->host_blob) (void)hipHostFree(plan->host_blob);
-    plan->ctx->used -= plan->blob_bytes;
+    plan->ctx->used -= plan->blob_bytes + plan->scratch_bytes;
     delete plan;
 }
 

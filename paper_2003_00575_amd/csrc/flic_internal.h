@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace flic {
@@ -10,22 +11,41 @@ namespace flic {
 // Pixels per workgroup tile held in LDS (range + union-find parent per pixel).
 constexpr int kTilePx = 8192;
 constexpr int kMaxSkip = 8;
-constexpr int kThreads = 256;
 
 // Per-scan descriptor as the kernels read it (device memory, or a kernel
 // argument for the single-scan path).
+//
+// Scratch (device memory owned by the library, per scan):
+//   masks   [H][chunks_per_row] pairs of uint64: bit x of .x marks the first
+//           pixel of a run (maximal row segment joined by direct horizontal
+//           edges) in that 64-pixel row chunk, bit x of .y a measurement.
+//   parent  [H*W] int32, used only at tile-root positions: the global
+//           union-find of the tile components (written for every tile root
+//           by pass 1, joined by pass 2, read by pass 3).
+//   bcol_v / bcol_r  [tiles][2][N][tile_h]: range and provisional root of the
+//           first (side 0) and last (side 1) N columns of each tile.
+//   brow_v / brow_r  [tiles][2][N][tile_w]: the same for the first and last N
+//           rows; present only when the scan has more than one tile row.
+// Between passes 1 and 3 the label array holds, at the start of each row
+// chunk, the global root of every run of that chunk in order.
 struct ScanDesc {
     const float* range;     // [H][W]
     int32_t* labels;        // [H][W]
     const float* cos_v;     // [N][H]
     const float* cos_h;     // [N][W]
+    ulonglong2* masks;
+    int32_t* parent;
+    float* bcol_v;
+    int32_t* bcol_r;
+    float* brow_v;
+    int32_t* brow_r;
     int32_t H, W, N;
     float t2;               // fl32(T*T)
     int32_t tile_w;         // tile columns
     int32_t tile_h;         // tile rows (kTilePx / tile_w)
     int32_t tiles_x, tiles_y;
+    int32_t chunks_per_row; // ceil(W / 64)
     int32_t tile_begin;     // first global tile id of this scan in its batch
-    int32_t pad_;
 };
 
 // Where a launch finds its scans: a device table plus a block -> scan map,
@@ -38,13 +58,38 @@ struct BatchRef {
 
 inline int tile_h_for(int tile_w) { return kTilePx / tile_w; }
 
+// Scratch bytes one scan needs, and the sub-buffer offsets (each 256-byte
+// aligned) relative to the scan's scratch base.
+struct ScratchLayout {
+    size_t masks, parent, bcol_v, bcol_r, brow_v, brow_r, total;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline ScratchLayout scratch_layout(int H, int W, int N, int tile_w) {
+    const int tile_h = tile_h_for(tile_w);
+    const size_t tiles = (size_t)((W + tile_w - 1) / tile_w) * ((H + tile_h - 1) / tile_h);
+    const bool rows = H > tile_h;
+    ScratchLayout L{};
+    size_t o = 0;
+    L.masks = o;  o = align256(o + (size_t)H * ((W + 63) / 64) * 16);
+    L.parent = o; o = align256(o + (size_t)H * W * 4);
+    L.bcol_v = o; o = align256(o + tiles * 2 * N * tile_h * 4);
+    L.bcol_r = o; o = align256(o + tiles * 2 * N * tile_h * 4);
+    L.brow_v = o; o = align256(o + (rows ? tiles * 2 * N * tile_w * 4 : 0));
+    L.brow_r = o; o = align256(o + (rows ? tiles * 2 * N * tile_w * 4 : 0));
+    L.total = o;
+    return L;
+}
+
 constexpr int kPasses = 3;
 
-// Enqueue the three passes (tile labelling, border merge, relabel) for
-// `n_tiles` tiles of width `tile_w` (64, 128 or 256), all of skip depth
-// `skip` (1..kMaxSkip).  When `events` is non-null, events[0] is recorded
-// before the first pass and events[i + 1] after pass i.
-hipError_t launch_cluster(const BatchRef& ref, int tile_w, int skip, int n_tiles,
+// Enqueue the three passes (tile labelling, scan merge, relabel) for
+// `n_scans` scans with `n_tiles` tiles in total, of tile width `tile_w`
+// (64, 128 or 256) and skip depth `skip` (1..kMaxSkip).  When `events` is
+// non-null, events[0] is recorded before the first pass and events[i + 1]
+// after pass i.
+hipError_t launch_cluster(const BatchRef& ref, int tile_w, int skip, int n_tiles, int n_scans,
                           hipStream_t stream, hipEvent_t* events = nullptr);
 
 }  // namespace flic

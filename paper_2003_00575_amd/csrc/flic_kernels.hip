@@ -4,7 +4,7 @@
 // tile_h rows x tile_w columns (tile_h * tile_w = kTilePx, tile_w a multiple
 // of the 64-lane wavefront):
 //
-//   k_tile_label    one workgroup per tile.
+//   k_tile_label   one workgroup per tile.
 //     load   coalesced (float4 where aligned) copy of the tile's ranges into
 //            LDS, missing pixels replaced by NaN; the tile's slices of the
 //            angle tables staged in LDS as 2*cos.
@@ -14,22 +14,26 @@
 //     runs   the k = 1 horizontal ballot gives the row runs directly: every
 //            pixel's parent is the first pixel of its run in the chunk.
 //     union  only edges not already implied are joined in an LDS union-find
-//            (atomicMin hooking of the larger root under the smaller):
-//            an edge is implied when the same edge one pixel to the left
-//            exists and both of its ends continue into this edge's ends
-//            along a run, when a k-step horizontal edge stays inside a run,
-//            or when a k-step vertical edge is covered by k direct ones.
-//     write  provisional label = global linear index of the pixel's tile
-//            root (the tile component's minimum), -1 for missing pixels.
-//   k_border_merge  one workgroup per tile: the edges leaving the tile to the
-//            right (including the 360-degree wrap seam) and downwards, with
-//            the same left-neighbour implication along the border, joined in
-//            a global union-find whose parent array is the label array
-//            itself (labels[p] <= p always points into p's component; roots
-//            satisfy labels[r] == r; hooks are atomicMin).
-//   k_relabel  one workgroup per tile: labels[p] = root(labels[p]).  The root
-//            of a component is its minimum linear index, since a hook only
-//            ever moves a larger root under a smaller one.
+//            (atomicMin hooking of the larger root under the smaller): an
+//            edge is implied when the same edge one pixel to the left exists
+//            and both of its ends continue into this edge's ends along a run,
+//            when a k-step horizontal edge stays inside a run, or when a
+//            k-step vertical edge is covered by k direct ones.
+//     output the chunk's run and measurement masks; at the start of the
+//            chunk's label row segment, the global root (tile component
+//            minimum) of each run in order; the range and root of the tile's
+//            border columns (and rows); parent[root] = root for every tile
+//            root.  No per-pixel label is written yet.
+//   k_scan_merge   one workgroup per scan: tests the edges between tiles
+//            (tile columns including the 360-degree seam, tile rows) from the
+//            compact border arrays, prunes implied ones, deduplicates them to
+//            pairs of tile roots and joins those in the parent array; every
+//            joined root is then pointed at its final root.  A root only ever
+//            hooks under a smaller one, so a component's final root is its
+//            minimum linear index.
+//   k_relabel      one workgroup per tile: expands the run lists through the
+//            parent array into the final labels, one coalesced store per
+//            pixel.
 //
 // The edge test is bit-identical to a scalar binary32 evaluation: contraction
 // is off for the whole file (the build checks the ISA has no fused
@@ -43,12 +47,8 @@
 namespace flic {
 namespace {
 
-constexpr int kLabelThreads = 512;     // 8 wavefronts per tile in k_tile_label
+constexpr int kLabelThreads = 1024;    // 16 wavefronts per tile in k_tile_label
 constexpr int kLabelWaves = kLabelThreads / 64;
-
-__device__ __forceinline__ bool is_measurement(float r) {
-    return (r > 0.0f) && (r < __builtin_inff());
-}
 
 // Eq. (4): (d1*d1 + d2*d2) - ((2 cos a) * (d1*d2)) <= T^2, each op rounded.
 __device__ __forceinline__ bool connected(float d1, float d2, float two_cos, float t2) {
@@ -61,8 +61,9 @@ __device__ __forceinline__ bool connected(float d1, float d2, float two_cos, flo
     return dist2 <= t2;
 }
 
+// A measurement is a positive normal or subnormal number (one class test).
 __device__ __forceinline__ float measurement_or_nan(float r) {
-    return is_measurement(r) ? r : __builtin_nanf("");
+    return __builtin_amdgcn_class(r, (1 << 7) | (1 << 8)) ? r : __builtin_nanf("");
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
@@ -109,46 +110,43 @@ __device__ void lds_unite(int* par, int a, int b) {
     }
 }
 
-// ---- union-find on the global label array ---------------------------------
-
-__device__ __forceinline__ int g_load(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ int g_find(int* par, int x) {
-    int p = g_load(&par[x]);
-    while (p != x) {
-        x = p;
-        p = g_load(&par[x]);
-    }
-    return x;
-}
-
-__device__ void g_unite(int* par, int a, int b) {
-    for (;;) {
-        a = g_find(par, a);
-        b = g_find(par, b);
-        if (a == b) return;
-        if (a > b) { int t = a; a = b; b = t; }
-        const int old = __hip_atomic_fetch_min(&par[b], a, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        if (old == b) return;
-        b = old;
-    }
-}
-
 // ---- pass 1: tile-local labelling ------------------------------------------
+//
+// LDS holds the tile's ranges with kPad extra NaN columns on the right and
+// kPad extra NaN rows below, so every neighbour read is in bounds and an edge
+// that leaves the tile simply tests false (those edges belong to pass 2).
+// Each wavefront owns one 64-column strip of 8 consecutive rows and walks it
+// bottom-up, keeping the values, squares and direct-edge ballots of the N
+// rows below in registers.
+
+constexpr int kPad = 8;            // >= kMaxSkip
+constexpr int kRowsPerWave = 8;    // kTilePx / 64 / kLabelWaves
+
+// Eq. (4) with both squares already formed: (sq1 + sq2) - ((2 cos a) * (d1 * d2)).
+__device__ __forceinline__ bool connected_sq(float d1, float sq1, float d2, float sq2,
+                                             float two_cos, float t2) {
+    float sum = sq1 + sq2;
+    float prod = d1 * d2;
+    float cross = two_cos * prod;
+    float dist2 = sum - cross;
+    return dist2 <= t2;
+}
+
+__device__ __forceinline__ bool lane_bit(uint64_t mask) {
+    return __builtin_amdgcn_inverse_ballot_w64(mask);
+}
 
 template <int TW, int N>
-__global__ __launch_bounds__(kLabelThreads) void k_tile_label(BatchRef ref) {
+__global__ __launch_bounds__(kLabelThreads) __attribute__((amdgpu_waves_per_eu(N <= 3 ? 8 : 4)))
+void k_tile_label(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
-    constexpr int CH = TW / 64;               // 64-column chunks per tile row
-    __shared__ float rs[kTilePx];
+    constexpr int CH = TW / 64;               // 64-column strips per tile row
+    constexpr int RS = TW + kPad;             // LDS row stride of the ranges
+    static_assert(TH * CH == kLabelWaves * kRowsPerWave, "one 8-row strip per wavefront");
+    __shared__ float rs[(TH + kPad) * RS];
     __shared__ int par[kTilePx];
-    __shared__ uint64_t mh[N][TH * CH];       // horizontal edge ballots, k = 1..N
-    __shared__ uint64_t mv[N][TH * CH];       // vertical edge ballots, k = 1..N
     __shared__ float c2h[N][TW];
-    __shared__ float c2v[N][TH];
+    __shared__ float c2v[N][TH + kPad];
 
     ScanDesc d;
     int tile;
@@ -159,200 +157,409 @@ __global__ __launch_bounds__(kLabelThreads) void k_tile_label(BatchRef ref) {
     const int W = d.W, H = d.H;
     const float t2 = d.t2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float nan = __builtin_nanf("");
 
     for (int i = threadIdx.x; i < N * TW; i += kLabelThreads) {
         const int k = i / TW, c = i % TW;
         c2h[k][c] = (c < tw) ? 2.0f * d.cos_h[(size_t)k * W + c0 + c] : 0.0f;
     }
-    for (int i = threadIdx.x; i < N * TH; i += kLabelThreads) {
-        const int k = i / TH, r = i % TH;
+    for (int i = threadIdx.x; i < N * (TH + kPad); i += kLabelThreads) {
+        const int k = i / (TH + kPad), r = i % (TH + kPad);
         c2v[k][r] = (r < th && r0 + r + k + 1 < H) ? 2.0f * d.cos_v[(size_t)k * H + r0 + r] : 0.0f;
     }
     const float* src = d.range + (size_t)r0 * W + c0;
     if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(d.range) & 15) == 0) {
         // tw is then a multiple of 4 as well
-        constexpr int Q = TW / 4;
-        for (int i = threadIdx.x; i < th * Q; i += kLabelThreads) {
+        constexpr int Q = RS / 4;
+        for (int i = threadIdx.x; i < (TH + kPad) * Q; i += kLabelThreads) {
             const int lr = i / Q, lc = (i % Q) * 4;
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (lc < tw) v = *reinterpret_cast<const float4*>(src + (size_t)lr * W + lc);
-            v.x = measurement_or_nan(v.x);
-            v.y = measurement_or_nan(v.y);
-            v.z = measurement_or_nan(v.z);
-            v.w = measurement_or_nan(v.w);
-            *reinterpret_cast<float4*>(&rs[lr * TW + lc]) = v;
+            float4 v = make_float4(nan, nan, nan, nan);
+            if (lr < th && lc < tw) {
+                v = *reinterpret_cast<const float4*>(src + (size_t)lr * W + lc);
+                v.x = measurement_or_nan(v.x);
+                v.y = measurement_or_nan(v.y);
+                v.z = measurement_or_nan(v.z);
+                v.w = measurement_or_nan(v.w);
+            }
+            *reinterpret_cast<float4*>(&rs[lr * RS + lc]) = v;
         }
     } else {
-        for (int i = threadIdx.x; i < th * TW; i += kLabelThreads) {
-            const int lr = i / TW, lc = i % TW;
-            rs[i] = measurement_or_nan(lc < tw ? src[(size_t)lr * W + lc] : 0.0f);
+        for (int i = threadIdx.x; i < (TH + kPad) * RS; i += kLabelThreads) {
+            const int lr = i / RS, lc = i % RS;
+            rs[i] = (lr < th && lc < tw) ? measurement_or_nan(src[(size_t)lr * W + lc]) : nan;
         }
     }
     __syncthreads();
 
-    // edges -> ballots; runs -> parents
-    for (int item = wave; item < th * CH; item += kLabelWaves) {
-        const int r = item / CH, ch = item % CH;
-        const int c = ch * 64 + lane, i = r * TW + c;
-        const float a = rs[i];
-        uint64_t h1 = 0;
+    const int ch = wave % CH, R0 = (wave / CH) * kRowsPerWave;
+    const int c = ch * 64 + lane;
+    const uint64_t le = lanes_le(lane);
+    float c2hk[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) c2hk[k] = c2h[k][c];
+
+    // Window of the N rows below the current one: value, square, direct
+    // horizontal ballot (h1) and direct vertical ballot (v1) of each.
+    float wv[N], ws[N];
+    uint64_t wh1[N], wv1[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int q = R0 + kRowsPerWave + j;            // < TH + kPad
+        wv[j] = rs[q * RS + c];
+        ws[j] = wv[j] * wv[j];
+        const float right = rs[q * RS + c + 1];
+        const float below = rs[(q + 1 < TH + kPad ? q + 1 : q) * RS + c];
+        wh1[j] = ballot(connected_sq(wv[j], ws[j], right, right * right, c2hk[0], t2));
+        wv1[j] = (q + 1 < TH + kPad)
+                     ? ballot(connected_sq(wv[j], ws[j], below, below * below, c2v[0][q], t2))
+                     : 0;
+    }
+
+    // Edge ballots row by row (bottom-up).  todo bit 0: the next pixel
+    // across a strip border; bit k (1..N): k rows down; bit N+k-1 (k >= 2):
+    // k columns right.  A bit is set only when the edge is not implied.
+    uint32_t todo[kRowsPerWave];
+    uint32_t heads = 0, valids = 0;                      // bit j: row R0 + j
+#pragma unroll
+    for (int j = kRowsPerWave - 1; j >= 0; --j) {
+        const int r = R0 + j;
+        const float a = rs[r * RS + c];
+        const float sa = a * a;
+        uint64_t h1 = 0, v1 = 0, chain = 0, run = 0;
+        uint32_t t = 0;
 #pragma unroll
         for (int k = 1; k <= N; ++k) {
-            bool eh = false, ev = false;
-            if (c + k < tw) eh = connected(a, rs[i + k], c2h[k - 1][c], t2);
-            if (r + k < th) ev = connected(a, rs[i + k * TW], c2v[k - 1][r], t2);
-            const uint64_t hm = ballot(eh), vm = ballot(ev);
-            if (lane == 0) {
-                mh[k - 1][item] = hm;
-                mv[k - 1][item] = vm;
+            const float b = rs[r * RS + c + k];
+            const uint64_t hk = ballot(connected_sq(a, sa, b, b * b, c2hk[k - 1], t2));
+            const uint64_t vk = ballot(connected_sq(a, sa, wv[k - 1], ws[k - 1], c2v[k - 1][r], t2));
+            if (k == 1) {
+                h1 = hk;
+                v1 = vk;
+                chain = vk;
+                run = hk;
+                if (CH > 1 && ch + 1 < CH && lane == 63 && (h1 >> 63)) t |= 1u;
+            } else {
+                chain &= wv1[k - 2];
+                run &= h1 >> (k - 1);
+                const uint64_t hneed = hk & ~run & ~((hk & h1 & (h1 >> k)) << 1);
+                if (lane_bit(hneed)) t |= 1u << (N + k - 1);
             }
-            if (k == 1) h1 = hm;
+            uint64_t vneed = vk & ~((vk & h1 & wh1[k - 1]) << 1);
+            if (k >= 2) vneed &= ~chain;
+            if (lane_bit(vneed)) t |= 1u << k;
         }
-        const uint64_t starts = ~(h1 << 1);           // bit j: no edge from j-1 into j
-        const int head = 63 - __clzll(starts & lanes_le(lane));
-        par[i] = (a == a) ? r * TW + ch * 64 + head : -1;
+        todo[j] = t;
+        const bool valid = a == a;
+        const int head = 63 - __clzll(~(h1 << 1) & le);   // first pixel of the run
+        par[r * TW + c] = valid ? r * TW + ch * 64 + head : -1;
+        if (valid && head == lane) heads |= 1u << j;
+        if (valid) valids |= 1u << j;
+#pragma unroll
+        for (int k = N - 1; k >= 1; --k) {
+            wv[k] = wv[k - 1];
+            ws[k] = ws[k - 1];
+            wh1[k] = wh1[k - 1];
+            wv1[k] = wv1[k - 1];
+        }
+        wv[0] = a;
+        ws[0] = sa;
+        wh1[0] = h1;
+        wv1[0] = v1;
+        // keep rows apart: interleaving them only raises scalar-register pressure
+        __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
 
-    // unions for the edges that are not implied
-    for (int item = wave; item < th * CH; item += kLabelWaves) {
-        const int r = item / CH, ch = item % CH;
-        const int c = ch * 64 + lane, i = r * TW + c;
-        const uint64_t h1 = mh[0][item];
-        if (CH > 1 && ch + 1 < CH && lane == 63 && (h1 >> 63)) lds_unite(par, i, i + 1);
-        uint64_t chain = mv[0][item];                 // direct vertical edges rows r..r+k
 #pragma unroll
-        for (int k = 1; k <= N; ++k) {
-            if (r + k >= th) break;
-            const uint64_t vk = mv[k - 1][item];
-            if (k >= 2) chain &= mv[0][(r + k - 1) * CH + ch];
-            uint64_t need = vk & ~((vk & h1 & mh[0][(r + k) * CH + ch]) << 1);
-            if (k >= 2) need &= ~chain;
-            if ((need >> lane) & 1) lds_unite(par, i, i + k * TW);
-        }
-        uint64_t run = h1;                            // run: bits j..j+k-1 of h1 all set
-#pragma unroll
-        for (int k = 2; k <= N; ++k) {
-            run &= h1 >> (k - 1);
-            const uint64_t hk = mh[k - 1][item];
-            const uint64_t need = hk & ~run & ~((hk & h1 & (h1 >> k)) << 1);
-            if ((need >> lane) & 1) lds_unite(par, i, i + k);
+    for (int j = 0; j < kRowsPerWave; ++j) {
+        const int i = (R0 + j) * TW + c;
+        uint32_t t = todo[j];
+        if (ballot(t != 0) == 0) continue;              // nothing to join in this row
+        while (t) {
+            const int b = __builtin_ctz(t);
+            t &= t - 1;
+            const int other = b == 0 ? i + 1 : (b <= N ? i + b * TW : i + (b - N + 1));
+            lds_unite(par, i, other);
         }
     }
     __syncthreads();
 
-    int* dst = d.labels + (size_t)r0 * W + c0;
-    for (int item = wave; item < th * CH; item += kLabelWaves) {
-        const int r = item / CH, ch = item % CH;
-        const int c = ch * 64 + lane, i = r * TW + c;
-        if (c < tw) {
-            const int p = par[i];
-            int out = -1;
-            if (p >= 0) {
-                const int root = lds_find(par, p);
-                out = (r0 + root / TW) * W + c0 + root % TW;
-            }
-            dst[(size_t)r * W + c] = out;
+    // Output 1: per row chunk, the run / measurement masks, the global root
+    // of each run at the start of the chunk's label segment, and
+    // parent[root] = root for every tile root.
+    const int base = r0 * W + c0;
+    const bool chunk_in = ch * 64 < tw;                  // chunk lies in the image
+    ulonglong2* mrow = d.masks + (size_t)r0 * d.chunks_per_row + c0 / 64 + ch;
+    int* lrow = d.labels + (size_t)r0 * W + c0 + ch * 64;
+    const uint64_t below = le >> 1;                       // lanes < lane
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) {
+        const int r = R0 + j;
+        if (r >= th || !chunk_in) break;
+        const bool head = (heads >> j) & 1;
+        const uint64_t vmask = ballot((valids >> j) & 1);
+        const uint64_t starts = ballot(head);
+        if (lane == 0) mrow[(size_t)r * d.chunks_per_row] = make_ulonglong2(starts, vmask);
+        if (head) {
+            const int i = r * TW + c;
+            const int root = lds_find(par, i);
+            const int groot = base + (root / TW) * W + (root % TW);
+            lrow[(size_t)r * W + __popcll(starts & below)] = groot;
+            if (root == i) d.parent[groot] = groot;
+        }
+    }
+
+    // Output 2: range and global root of the border columns (and rows),
+    // one thread per border pixel, contiguous along the border.
+    const bool many_rows = d.tiles_y > 1;
+    const int ncol_items = 2 * N * th;
+    const int nrow_items = many_rows ? 2 * N * tw : 0;
+    for (int it = threadIdx.x; it < ncol_items + nrow_items; it += kLabelThreads) {
+        int rr, cc;
+        size_t at;
+        bool side_col;
+        if (it < ncol_items) {
+            const int side = it / (N * th), rem = it % (N * th);
+            const int slot = rem / th;
+            rr = rem % th;
+            cc = side == 0 ? slot : tw - N + slot;
+            at = (((size_t)tile * 2 + side) * N + slot) * TH + rr;
+            side_col = true;
+        } else {
+            const int k = it - ncol_items;
+            const int side = k / (N * tw), rem = k % (N * tw);
+            const int slot = rem / tw;
+            cc = rem % tw;
+            rr = side == 0 ? slot : th - N + slot;
+            at = (((size_t)tile * 2 + side) * N + slot) * TW + cc;
+            side_col = false;
+        }
+        if (cc < 0 || cc >= tw || rr < 0 || rr >= th) continue;   // tile narrower than N
+        const float v = rs[rr * RS + cc];
+        const int p = par[rr * TW + cc];
+        int groot = -1;
+        if (p >= 0) {
+            const int root = lds_find(par, p);
+            groot = base + (root / TW) * W + (root % TW);
+        }
+        if (side_col) {
+            d.bcol_v[at] = v;
+            d.bcol_r[at] = groot;
+        } else {
+            d.brow_v[at] = v;
+            d.brow_r[at] = groot;
         }
     }
 }
 
-// ---- pass 2: edges leaving the tile (right, wrap seam, down) ---------------
+// ---- pass 2: edges between tiles, one workgroup per scan ------------------
+//
+// Only this workgroup touches the scan's parent array during the pass, so
+// the union-find needs no cross-workgroup coherence: atomics and loads are
+// workgroup-scope (performed at / read from the L2 of this CU's XCD).
+// Border values and roots come from the compact arrays written by pass 1;
+// lane = row along a tile column border, lane = column along a tile row
+// border.  An edge is skipped when the same edge one row up (one column
+// left) exists and both its ends continue into this edge's ends by a direct
+// edge inside their tiles.  Remaining edges become (root, root) pairs; each
+// wavefront drops repeats and appends the rest to an LDS list, which is then
+// joined in parallel and compressed.
+
+constexpr int kMergeThreads = 1024;
+constexpr int kMaxPairs = 6144;
+
+__device__ __forceinline__ int wg_load(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int wg_find(int* par, int x) {
+    int p = wg_load(&par[x]);
+    while (p != x) {
+        x = p;
+        p = wg_load(&par[x]);
+    }
+    return x;
+}
+
+__device__ void wg_unite(int* par, int a, int b) {
+    for (;;) {
+        a = wg_find(par, a);
+        b = wg_find(par, b);
+        if (a == b) return;
+        if (a > b) { int t = a; a = b; b = t; }
+        const int old = __hip_atomic_fetch_min(&par[b], a, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == b) return;
+        b = old;
+    }
+}
+
+// Append the distinct (a, b) pairs held by active lanes to the LDS list
+// (joining directly when the list is full).
+__device__ __forceinline__ void push_pairs(bool act, int a, int b, int2* list, int* count,
+                                           int* par, int lane) {
+    for (;;) {
+        const uint64_t m = ballot(act);
+        if (m == 0) return;
+        const int leader = __builtin_ctzll(m);
+        const int la = __shfl(a, leader), lb = __shfl(b, leader);
+        if (act && a == la && b == lb) act = false;
+        if (lane == leader) {
+            const int slot = atomicAdd(count, 1);
+            if (slot < kMaxPairs) list[slot] = make_int2(la, lb);
+            else wg_unite(par, la, lb);
+        }
+    }
+}
 
 template <int TW, int N>
-__global__ __launch_bounds__(kThreads) void k_border_merge(BatchRef ref) {
+__global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
-    constexpr int kWaves = kThreads / 64;
-    ScanDesc d;
-    int tile;
-    locate(ref, blockIdx.x, d, tile);
-    const int tx = tile % d.tiles_x, ty = tile / d.tiles_x;
-    const int c0 = tx * TW, r0 = ty * TH;
-    const int tw = min(TW, d.W - c0), th = min(TH, d.H - r0);
+    constexpr int kWaves = kMergeThreads / 64;
+    __shared__ int2 list[kMaxPairs];
+    __shared__ int count;
+
+    const ScanDesc d = ref.descs ? ref.descs[blockIdx.x] : ref.one;
     const int W = d.W, H = d.H;
     const float t2 = d.t2;
-    const int col_end = c0 + tw, row_end = r0 + th;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int* lab = d.labels;
-    const float nan = __builtin_nanf("");
+    int* par = d.parent;
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
 
-    // Right border: source column c = col_end - nc + j (j < nc), offset k with
-    // c + k >= col_end, target column (c + k) mod W.  Pairs (j, k) enumerate
-    // k = nc - j .. N.  Lane = row within a 64-row chunk.
-    const int nc = min(N, tw);
-    const int npairs = nc * N - nc * (nc - 1) / 2;    // sum over j of (N - (nc - j) + 1)
-    const int rchunks = (th + 63) / 64;
-    for (int it = wave; it < npairs * rchunks; it += kWaves) {
-        int pr = it / rchunks;
-        const int rc = it % rchunks;
-        int j = 0;
-        while (pr >= N - (nc - j) + 1) { pr -= N - (nc - j) + 1; ++j; }
-        const int k = nc - j + pr;
-        const int c = col_end - nc + j;
-        int t = c + k;
-        if (t >= W) t -= W;
-        const int r = r0 + rc * 64 + lane;
-        const bool in = r < row_end;
-        const float a = in ? measurement_or_nan(d.range[(size_t)r * W + c]) : nan;
-        const float b = in ? measurement_or_nan(d.range[(size_t)r * W + t]) : nan;
-        const bool e = connected(a, b, 2.0f * d.cos_h[(size_t)(k - 1) * W + c], t2);
-        // direct vertical edges from row r-1 on both sides (same band only)
-        const float ap = __shfl_up(a, 1), bp = __shfl_up(b, 1);
-        bool vv = false;
-        if (lane > 0 && in) {
-            const float cv = 2.0f * d.cos_v[r - 1];
-            vv = connected(ap, a, cv, t2) && connected(bp, b, cv, t2);
+    // tile column borders: item = (tile, 64-row chunk); the tile's last N
+    // columns against the next N columns to its right (mod W)
+    constexpr int RCH = (TH + 63) / 64;
+    const int n_tiles = d.tiles_x * d.tiles_y;
+    for (int it = wave; it < n_tiles * RCH; it += kWaves) {
+        const int t = it / RCH, rc = it % RCH;
+        const int tx = t % d.tiles_x, ty = t / d.tiles_x;
+        const int col_end = min((tx + 1) * TW, W);
+        const int nc = min(N, col_end - tx * TW);
+        const int th = min(TH, H - ty * TH);
+        const int lr = rc * 64 + lane;
+        if (rc * 64 >= th) continue;
+        const bool in = lr < th;
+        const int row = ty * TH + lr;
+        const size_t src_side = ((size_t)t * 2 + 1) * N * TH;
+        float vs[N], vt[N];
+        int rsrc[N], rtgt[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const bool ok = in && j >= N - nc;
+            vs[j] = ok ? d.bcol_v[src_side + (size_t)j * TH + lr] : __builtin_nanf("");
+            rsrc[j] = ok ? d.bcol_r[src_side + (size_t)j * TH + lr] : -1;
+            int q = col_end + j;
+            if (q >= W) q -= W;
+            const int u = q / TW, o = q - u * TW;
+            const size_t tgt_side = ((size_t)(ty * d.tiles_x + u) * 2 + 0) * N * TH;
+            vt[j] = in ? d.bcol_v[tgt_side + (size_t)o * TH + lr] : __builtin_nanf("");
+            rtgt[j] = in ? d.bcol_r[tgt_side + (size_t)o * TH + lr] : -1;
         }
-        const uint64_t E = ballot(e), V = ballot(vv);
-        const uint64_t need = E & ~((E << 1) & V);
-        if ((need >> lane) & 1) g_unite(lab, r * W + c, r * W + t);
+        // direct vertical edges from row - 1 (same tile row, lane > 0)
+        const bool up_ok = lane > 0 && in;
+        const float cv = up_ok ? 2.0f * d.cos_v[row - 1] : 0.0f;
+        bool us[N], ut[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            us[j] = up_ok && connected(__shfl_up(vs[j], 1), vs[j], cv, t2);
+            ut[j] = up_ok && connected(__shfl_up(vt[j], 1), vt[j], cv, t2);
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (j < N - nc) continue;
+            const int c = col_end - N + j;
+#pragma unroll
+            for (int k = 1; k <= N; ++k) {
+                const int m = j + k - N;                 // target slot
+                if (m < 0) continue;
+                const bool e = connected(vs[j], vt[m], 2.0f * d.cos_h[(size_t)(k - 1) * W + c], t2);
+                const uint64_t E = ballot(e);
+                const uint64_t V = ballot(us[j] && ut[m]);
+                const bool need = lane_bit(E & ~((E << 1) & V));
+                push_pairs(need, rsrc[j], rtgt[m], list, &count, par, lane);
+            }
+        }
     }
 
-    // Bottom border, when another tile row follows: source row s = row_end -
-    // nr + j, offset k with s + k >= row_end and s + k < H.  Lane = column.
-    if (row_end < H) {
-        const int nr = min(N, th);
-        const int npv = nr * N - nr * (nr - 1) / 2;
-        const int cchunks = (tw + 63) / 64;
-        for (int it = wave; it < npv * cchunks; it += kWaves) {
-            int pr = it / cchunks;
-            const int cc = it % cchunks;
-            int j = 0;
-            while (pr >= N - (nr - j) + 1) { pr -= N - (nr - j) + 1; ++j; }
-            const int k = nr - j + pr;
-            const int s = row_end - nr + j;
-            const int c = c0 + cc * 64 + lane;
-            const bool in = (c < col_end) && (s + k < H);
-            const float a = in ? measurement_or_nan(d.range[(size_t)s * W + c]) : nan;
-            const float b = in ? measurement_or_nan(d.range[(size_t)(s + k) * W + c]) : nan;
-            const bool e = in && connected(a, b, 2.0f * d.cos_v[(size_t)(k - 1) * H + s], t2);
-            const float ap = __shfl_up(a, 1), bp = __shfl_up(b, 1);
-            bool hl = false;
-            if (lane > 0 && in) {
-                hl = connected(ap, a, 2.0f * d.cos_h[c - 1], t2) &&
-                     connected(bp, b, 2.0f * d.cos_h[c - 1], t2);
+    // tile row borders (only with several tile rows): item = (tile above,
+    // 64-column chunk); its last N rows against the next N rows below
+    if (d.tiles_y > 1) {
+        constexpr int CCH = TW / 64;
+        const int n_upper = d.tiles_x * (d.tiles_y - 1);
+        for (int it = wave; it < n_upper * CCH; it += kWaves) {
+            const int t = it / CCH, cc = it % CCH;
+            const int tx = t % d.tiles_x, ty = t / d.tiles_x;
+            const int tw = min(TW, W - tx * TW);
+            const int lc = cc * 64 + lane;
+            if (cc * 64 >= tw) continue;
+            const bool in = lc < tw;
+            const int col = tx * TW + lc;
+            const int row_end = (ty + 1) * TH;
+            const size_t src_side = ((size_t)t * 2 + 1) * N * TW;
+            const size_t tgt_side = ((size_t)((ty + 1) * d.tiles_x + tx) * 2 + 0) * N * TW;
+            float vs[N], vt[N];
+            int rsrc[N], rtgt[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                vs[j] = in ? d.brow_v[src_side + (size_t)j * TW + lc] : __builtin_nanf("");
+                rsrc[j] = in ? d.brow_r[src_side + (size_t)j * TW + lc] : -1;
+                const bool tok = in && row_end + j < H;
+                vt[j] = tok ? d.brow_v[tgt_side + (size_t)j * TW + lc] : __builtin_nanf("");
+                rtgt[j] = tok ? d.brow_r[tgt_side + (size_t)j * TW + lc] : -1;
             }
-            const uint64_t E = ballot(e), Hm = ballot(hl);
-            const uint64_t need = E & ~((E << 1) & Hm);
-            if ((need >> lane) & 1) g_unite(lab, s * W + c, (s + k) * W + c);
+            const bool left_ok = lane > 0 && in;
+            const float chh = left_ok ? 2.0f * d.cos_h[col - 1] : 0.0f;
+            bool ls[N], lt[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                ls[j] = left_ok && connected(__shfl_up(vs[j], 1), vs[j], chh, t2);
+                lt[j] = left_ok && connected(__shfl_up(vt[j], 1), vt[j], chh, t2);
+            }
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const int sr = row_end - N + j;
+#pragma unroll
+                for (int k = 1; k <= N; ++k) {
+                    const int m = j + k - N;
+                    if (m < 0 || row_end + m >= H) continue;
+                    const bool e = connected(vs[j], vt[m], 2.0f * d.cos_v[(size_t)(k - 1) * H + sr], t2);
+                    const uint64_t E = ballot(e);
+                    const uint64_t L = ballot(ls[j] && lt[m]);
+                    const bool need = lane_bit(E & ~((E << 1) & L));
+                    push_pairs(need, rsrc[j], rtgt[m], list, &count, par, lane);
+                }
+            }
         }
+    }
+    __syncthreads();
+
+    const int n = min(count, kMaxPairs);
+    for (int i = threadIdx.x; i < n; i += kMergeThreads) wg_unite(par, list[i].x, list[i].y);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kMergeThreads) {
+        const int a = list[i].x, b = list[i].y;
+        const int ra = wg_find(par, a);              // a and b now share this root
+        if (ra != a) par[a] = ra;
+        if (ra != b) par[b] = ra;
     }
 }
 
-// ---- pass 3: every pixel to its root ----------------------------------------
+// ---- pass 3: run lists -> labels ---------------------------------------------
 
-__device__ __forceinline__ int root_of(const int* lab, int l) {
-    int x = l, nx = lab[x];
-    while (nx != x) {
-        x = nx;
-        nx = lab[x];
+__device__ __forceinline__ int root_of(const int* par, int x) {
+    int p = par[x];
+    while (p != x) {
+        x = p;
+        p = par[x];
     }
     return x;
 }
 
 template <int TW>
-__global__ __launch_bounds__(kThreads) void k_relabel(BatchRef ref) {
+__global__ __launch_bounds__(kLabelThreads) void k_relabel(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
+    constexpr int CH = TW / 64;
     ScanDesc d;
     int tile;
     locate(ref, blockIdx.x, d, tile);
@@ -360,72 +567,79 @@ __global__ __launch_bounds__(kThreads) void k_relabel(BatchRef ref) {
     const int c0 = tx * TW, r0 = ty * TH;
     const int tw = min(TW, d.W - c0), th = min(TH, d.H - r0);
     const int W = d.W;
-    int* lab = d.labels;
-    int* base = lab + (size_t)r0 * W + c0;
-    if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(lab) & 15) == 0) {
-        constexpr int Q = TW / 4;
-        for (int i = threadIdx.x; i < th * Q; i += kThreads) {
-            const int lr = i / Q, lc = (i % Q) * 4;
-            if (lc >= tw) continue;
-            int4* p4 = reinterpret_cast<int4*>(base + (size_t)lr * W + lc);
-            const int4 l = *p4;
-            int4 f = l;
-            if (l.x >= 0) f.x = root_of(lab, l.x);
-            if (l.y >= 0) f.y = root_of(lab, l.y);
-            if (l.z >= 0) f.z = root_of(lab, l.z);
-            if (l.w >= 0) f.w = root_of(lab, l.w);
-            if (f.x != l.x || f.y != l.y || f.z != l.z || f.w != l.w) *p4 = f;
-        }
-    } else {
-        for (int i = threadIdx.x; i < th * TW; i += kThreads) {
-            const int lr = i / TW, lc = i % TW;
-            if (lc >= tw) continue;
-            int* p = base + (size_t)lr * W + lc;
-            const int l = *p;
-            if (l < 0) continue;
-            const int f = root_of(lab, l);
-            if (f != l) *p = f;
-        }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ch = wave % CH, R0 = (wave / CH) * kRowsPerWave;
+    const int c = ch * 64 + lane;
+    if (ch * 64 >= tw || R0 >= th) return;
+    const int rows = min(kRowsPerWave, th - R0);
+    const uint64_t le = lanes_le(lane);
+    const ulonglong2* mrow = d.masks + (size_t)(r0 + R0) * d.chunks_per_row + c0 / 64 + ch;
+    int* seg0 = d.labels + (size_t)(r0 + R0) * W + c0 + ch * 64;
+    const bool col_in = c < tw;
+    // all loads of the strip first: masks and run lists of every row ...
+    ulonglong2 m[kRowsPerWave];
+    int listed[kRowsPerWave];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) {
+        const bool row_in = j < rows;
+        m[j] = row_in ? mrow[(size_t)j * d.chunks_per_row] : make_ulonglong2(0, 0);
+        listed[j] = (row_in && col_in && lane < __popcll(m[j].x)) ? seg0[(size_t)j * W + lane] : -1;
     }
+    // ... then every pixel's run root and its final root ...
+    int out[kRowsPerWave];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) {
+        const int run = __popcll(m[j].x & le) - 1;
+        const int groot = __shfl(listed[j], run < 0 ? 0 : run);
+        out[j] = lane_bit(m[j].y) ? d.parent[groot] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j)
+        if (lane_bit(m[j].y) && out[j] != d.parent[out[j]]) out[j] = root_of(d.parent, out[j]);
+    // ... then the labels (the run lists are overwritten only now)
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j)
+        if (j < rows && col_in) seg0[(size_t)j * W + lane] = out[j];
 }
 
 template <int TW, int N>
-hipError_t launch_twn(const BatchRef& ref, int n_tiles, hipStream_t stream, hipEvent_t* ev) {
+hipError_t launch_twn(const BatchRef& ref, int n_tiles, int n_scans, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_tile_label<TW, N>), dim3(n_tiles), dim3(kLabelThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_border_merge<TW, N>), dim3(n_tiles), dim3(kThreads), 0, stream, ref);
+    hipLaunchKernelGGL((k_scan_merge<TW, N>), dim3(n_scans), dim3(kMergeThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_relabel<TW>, dim3(n_tiles), dim3(kThreads), 0, stream, ref);
+    hipLaunchKernelGGL(k_relabel<TW>, dim3(n_tiles), dim3(kLabelThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
 template <int TW>
-hipError_t launch_tw(const BatchRef& ref, int skip, int n_tiles, hipStream_t stream, hipEvent_t* ev) {
+hipError_t launch_tw(const BatchRef& ref, int skip, int n_tiles, int n_scans, hipStream_t stream,
+                     hipEvent_t* ev) {
     switch (skip) {
-        case 1: return launch_twn<TW, 1>(ref, n_tiles, stream, ev);
-        case 2: return launch_twn<TW, 2>(ref, n_tiles, stream, ev);
-        case 3: return launch_twn<TW, 3>(ref, n_tiles, stream, ev);
-        case 4: return launch_twn<TW, 4>(ref, n_tiles, stream, ev);
-        case 5: return launch_twn<TW, 5>(ref, n_tiles, stream, ev);
-        case 6: return launch_twn<TW, 6>(ref, n_tiles, stream, ev);
-        case 7: return launch_twn<TW, 7>(ref, n_tiles, stream, ev);
-        case 8: return launch_twn<TW, 8>(ref, n_tiles, stream, ev);
+        case 1: return launch_twn<TW, 1>(ref, n_tiles, n_scans, stream, ev);
+        case 2: return launch_twn<TW, 2>(ref, n_tiles, n_scans, stream, ev);
+        case 3: return launch_twn<TW, 3>(ref, n_tiles, n_scans, stream, ev);
+        case 4: return launch_twn<TW, 4>(ref, n_tiles, n_scans, stream, ev);
+        case 5: return launch_twn<TW, 5>(ref, n_tiles, n_scans, stream, ev);
+        case 6: return launch_twn<TW, 6>(ref, n_tiles, n_scans, stream, ev);
+        case 7: return launch_twn<TW, 7>(ref, n_tiles, n_scans, stream, ev);
+        case 8: return launch_twn<TW, 8>(ref, n_tiles, n_scans, stream, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_cluster(const BatchRef& ref, int tile_w, int skip, int n_tiles,
+hipError_t launch_cluster(const BatchRef& ref, int tile_w, int skip, int n_tiles, int n_scans,
                           hipStream_t stream, hipEvent_t* events) {
-    if (n_tiles <= 0) return hipSuccess;
+    if (n_tiles <= 0 || n_scans <= 0) return hipSuccess;
     switch (tile_w) {
-        case 64: return launch_tw<64>(ref, skip, n_tiles, stream, events);
-        case 128: return launch_tw<128>(ref, skip, n_tiles, stream, events);
-        case 256: return launch_tw<256>(ref, skip, n_tiles, stream, events);
+        case 64: return launch_tw<64>(ref, skip, n_tiles, n_scans, stream, events);
+        case 128: return launch_tw<128>(ref, skip, n_tiles, n_scans, stream, events);
+        case 256: return launch_tw<256>(ref, skip, n_tiles, n_scans, stream, events);
         default: return hipErrorInvalidValue;
     }
 }
