@@ -366,16 +366,24 @@ void k_tile_label(BatchRef ref) {
 // joined in parallel and compressed.
 
 constexpr int kMergeThreads = 1024;
-constexpr int kMaxPairs = 6144;
+constexpr int kSetCap = 8192;                 // LDS hash set of (root, root) pairs
+constexpr int kMaxProbe = 32;
+constexpr unsigned long long kEmpty = ~0ull;
 
 __device__ __forceinline__ int wg_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Find with path halving: each visited node is re-pointed at its
+// grandparent.  atomicMin keeps this safe next to concurrent hooks: a parent
+// only ever moves to an ancestor (a smaller index in the same tree).
 __device__ __forceinline__ int wg_find(int* par, int x) {
     int p = wg_load(&par[x]);
     while (p != x) {
-        x = p;
+        const int g = wg_load(&par[p]);
+        if (g == p) return p;
+        __hip_atomic_fetch_min(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = g;
         p = wg_load(&par[x]);
     }
     return x;
@@ -394,37 +402,34 @@ __device__ void wg_unite(int* par, int a, int b) {
     }
 }
 
-// Append the distinct (a, b) pairs held by active lanes to the LDS list
-// (joining directly when the list is full).
-__device__ __forceinline__ void push_pairs(bool act, int a, int b, int2* list, int* count,
-                                           int* par, int lane) {
-    for (;;) {
-        const uint64_t m = ballot(act);
-        if (m == 0) return;
-        const int leader = __builtin_ctzll(m);
-        const int la = __shfl(a, leader), lb = __shfl(b, leader);
-        if (act && a == la && b == lb) act = false;
-        if (lane == leader) {
-            const int slot = atomicAdd(count, 1);
-            if (slot < kMaxPairs) list[slot] = make_int2(la, lb);
-            else wg_unite(par, la, lb);
-        }
+// Insert the (a, b) root pairs of the active lanes into the LDS hash set
+// (open addressing, 64-bit compare-and-swap), so each distinct pair is joined
+// once.  A pair that finds no slot within kMaxProbe probes is joined at once.
+__device__ __forceinline__ void push_pairs(bool act, int a, int b, unsigned long long* set,
+                                           int* par) {
+    if (!act) return;
+    const unsigned long long key = ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
+    unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 40) & (kSetCap - 1);
+    for (int probe = 0; probe < kMaxProbe; ++probe) {
+        const unsigned long long old = atomicCAS(&set[h], kEmpty, key);
+        if (old == kEmpty || old == key) return;
+        h = (h + 1) & (kSetCap - 1);
     }
+    wg_unite(par, a, b);
 }
 
 template <int TW, int N>
 __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
     constexpr int kWaves = kMergeThreads / 64;
-    __shared__ int2 list[kMaxPairs];
-    __shared__ int count;
+    __shared__ unsigned long long set[kSetCap];
 
     const ScanDesc d = ref.descs ? ref.descs[blockIdx.x] : ref.one;
     const int W = d.W, H = d.H;
     const float t2 = d.t2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int* par = d.parent;
-    if (threadIdx.x == 0) count = 0;
+    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) set[i] = kEmpty;
     __syncthreads();
 
     // tile column borders: item = (tile, 64-row chunk); the tile's last N
@@ -456,6 +461,14 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
             vt[j] = in ? d.bcol_v[tgt_side + (size_t)o * TH + lr] : __builtin_nanf("");
             rtgt[j] = in ? d.bcol_r[tgt_side + (size_t)o * TH + lr] : -1;
         }
+        // every table value the item needs, loaded before any data-dependent work
+        float c2h[N][N];
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int k = 1; k <= N; ++k)
+                c2h[j][k - 1] = (j >= N - nc && j + k >= N)
+                                    ? 2.0f * d.cos_h[(size_t)(k - 1) * W + col_end - N + j] : 0.0f;
         // direct vertical edges from row - 1 (same tile row, lane > 0)
         const bool up_ok = lane > 0 && in;
         const float cv = up_ok ? 2.0f * d.cos_v[row - 1] : 0.0f;
@@ -468,16 +481,15 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             if (j < N - nc) continue;
-            const int c = col_end - N + j;
 #pragma unroll
             for (int k = 1; k <= N; ++k) {
                 const int m = j + k - N;                 // target slot
                 if (m < 0) continue;
-                const bool e = connected(vs[j], vt[m], 2.0f * d.cos_h[(size_t)(k - 1) * W + c], t2);
+                const bool e = connected(vs[j], vt[m], c2h[j][k - 1], t2);
                 const uint64_t E = ballot(e);
                 const uint64_t V = ballot(us[j] && ut[m]);
                 const bool need = lane_bit(E & ~((E << 1) & V));
-                push_pairs(need, rsrc[j], rtgt[m], list, &count, par, lane);
+                push_pairs(need, rsrc[j], rtgt[m], set, par);
             }
         }
     }
@@ -508,6 +520,13 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
                 vt[j] = tok ? d.brow_v[tgt_side + (size_t)j * TW + lc] : __builtin_nanf("");
                 rtgt[j] = tok ? d.brow_r[tgt_side + (size_t)j * TW + lc] : -1;
             }
+            float c2v[N][N];
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+#pragma unroll
+                for (int k = 1; k <= N; ++k)
+                    c2v[j][k - 1] = (j + k >= N && row_end + j + k - N < H)
+                                        ? 2.0f * d.cos_v[(size_t)(k - 1) * H + row_end - N + j] : 0.0f;
             const bool left_ok = lane > 0 && in;
             const float chh = left_ok ? 2.0f * d.cos_h[col - 1] : 0.0f;
             bool ls[N], lt[N];
@@ -518,27 +537,30 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
             }
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                const int sr = row_end - N + j;
 #pragma unroll
                 for (int k = 1; k <= N; ++k) {
                     const int m = j + k - N;
                     if (m < 0 || row_end + m >= H) continue;
-                    const bool e = connected(vs[j], vt[m], 2.0f * d.cos_v[(size_t)(k - 1) * H + sr], t2);
+                    const bool e = connected(vs[j], vt[m], c2v[j][k - 1], t2);
                     const uint64_t E = ballot(e);
                     const uint64_t L = ballot(ls[j] && lt[m]);
                     const bool need = lane_bit(E & ~((E << 1) & L));
-                    push_pairs(need, rsrc[j], rtgt[m], list, &count, par, lane);
+                    push_pairs(need, rsrc[j], rtgt[m], set, par);
                 }
             }
         }
     }
     __syncthreads();
 
-    const int n = min(count, kMaxPairs);
-    for (int i = threadIdx.x; i < n; i += kMergeThreads) wg_unite(par, list[i].x, list[i].y);
+    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) {
+        const unsigned long long key = set[i];
+        if (key != kEmpty) wg_unite(par, (int)(key >> 32), (int)(key & 0xffffffffu));
+    }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kMergeThreads) {
-        const int a = list[i].x, b = list[i].y;
+    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) {
+        const unsigned long long key = set[i];
+        if (key == kEmpty) continue;
+        const int a = (int)(key >> 32), b = (int)(key & 0xffffffffu);
         const int ra = wg_find(par, a);              // a and b now share this root
         if (ra != a) par[a] = ra;
         if (ra != b) par[b] = ra;
