@@ -135,6 +135,22 @@ void flic_plan_destroy(flic_plan* plan);
  * do not depend on it.  Plans keep the width they were created with.       */
 flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w);
 
+/* Tile width for scans of exactly this shape and skip depth (an autotuner
+ * result): 64, 128 or 256 columns per tile, or 0 to remove the rule.  Rules
+ * apply to launches and plans created afterwards on this context; the
+ * global override of flic_set_tile_override takes precedence.  Labels do
+ * not depend on the tile width.                                            */
+flic_status flic_ctx_set_tile_rule(flic_ctx* ctx, int32_t H, int32_t W, int32_t skip_depth,
+                                   int32_t tile_w);
+
+/* The tile width the context would use for such a scan.                   */
+flic_status flic_ctx_tile_for(const flic_ctx* ctx, int32_t H, int32_t W, int32_t skip_depth,
+                              int32_t* tile_w);
+
+/* Device bytes the context and its plans currently hold (descriptor and
+ * scratch buffers); the budget given to flic_ctx_create caps this value.   */
+flic_status flic_ctx_bytes_in_use(const flic_ctx* ctx, size_t* bytes);
+
 /* Per-pass timing for measurement.  While enabled, every launch enqueued by
  * flic_cluster_async / flic_cluster_batched on this context records HIP
  * events on its stream around each of its kernels (plans are not timed).

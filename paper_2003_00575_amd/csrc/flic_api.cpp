@@ -113,6 +113,8 @@ struct flic_ctx {
     size_t budget = 0;          // 0 = unlimited
     size_t used = 0;            // device bytes held by this context and its plans
     int tile_override = 0;
+    struct TileRule { int32_t H, W, N, tile_w; };
+    std::vector<TileRule> rules;   // exact-shape tile widths (autotuner output)
     static constexpr int kRing = 4;
     struct Slot {
         void* host = nullptr;   // pinned descriptor staging
@@ -154,8 +156,11 @@ struct flic_plan {
 
 namespace {
 
-int choose_tile_w(const flic_ctx* ctx, int32_t H, int32_t W) {
+int choose_tile_w(const flic_ctx* ctx, int32_t H, int32_t W, int32_t N) {
     if (ctx && ctx->tile_override > 0) return ctx->tile_override;
+    if (ctx)
+        for (const auto& r : ctx->rules)
+            if (r.H == H && r.W == W && r.N == N) return r.tile_w;
     // One tile row whenever the scan fits: 128 rows x 64 columns, 64 x 128
     // or 32 x 256 (every tile holds kTilePx pixels).
     if (H <= 32 && W >= 256) return 256;
@@ -193,7 +198,7 @@ size_t scratch_bytes(const flic_ctx* ctx, const flic_scan* scans, int32_t n) {
     size_t total = 0;
     for (int32_t i = 0; i < n; ++i)
         total += flic::scratch_layout(scans[i].H, scans[i].W, scans[i].skip_depth,
-                                      choose_tile_w(ctx, scans[i].H, scans[i].W)).total;
+                                      choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth)).total;
     return total;
 }
 
@@ -218,13 +223,13 @@ void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, char* 
     for (int32_t i = 0; i < n; ++i) {
         base[i] = scratch + off;
         off += flic::scratch_layout(scans[i].H, scans[i].W, scans[i].skip_depth,
-                                    choose_tile_w(ctx, scans[i].H, scans[i].W)).total;
+                                    choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth)).total;
     }
     const int widths[3] = {64, 128, 256};
     for (int gi = 0; gi < 3 * FLIC_MAX_SKIP; ++gi) {
         Layout::G g{widths[gi / FLIC_MAX_SKIP], 1 + gi % FLIC_MAX_SKIP, 0, 0, 0, {}};
         for (int32_t i = 0; i < n; ++i)
-            if (choose_tile_w(ctx, scans[i].H, scans[i].W) == g.tile_w && scans[i].skip_depth == g.skip)
+            if (choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth) == g.tile_w && scans[i].skip_depth == g.skip)
                 g.members.push_back(i);
         if (g.members.empty()) continue;
         std::vector<ScanDesc> descs;
@@ -382,6 +387,33 @@ flic_status flic_set_tile_override(flic_ctx* ctx, int32_t tile_w) {
     return FLIC_OK;
 }
 
+flic_status flic_ctx_set_tile_rule(flic_ctx* ctx, int32_t H, int32_t W, int32_t skip_depth,
+                                   int32_t tile_w) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    if (H < 1 || W < 1 || skip_depth < 1 || skip_depth > FLIC_MAX_SKIP)
+        return fail(FLIC_EINVAL, "bad shape %dx%d N=%d", H, W, skip_depth);
+    if (tile_w != 0 && tile_w != 64 && tile_w != 128 && tile_w != 256)
+        return fail(FLIC_EINVAL, "tile_w %d not in {0, 64, 128, 256}", tile_w);
+    auto& v = ctx->rules;
+    for (size_t i = 0; i < v.size(); ++i)
+        if (v[i].H == H && v[i].W == W && v[i].N == skip_depth) { v.erase(v.begin() + i); break; }
+    if (tile_w) v.push_back({H, W, skip_depth, tile_w});
+    return FLIC_OK;
+}
+
+flic_status flic_ctx_tile_for(const flic_ctx* ctx, int32_t H, int32_t W, int32_t skip_depth,
+                              int32_t* tile_w) {
+    if (!ctx || !tile_w) return fail(FLIC_EINVAL, "null argument");
+    *tile_w = choose_tile_w(ctx, H, W, skip_depth);
+    return FLIC_OK;
+}
+
+flic_status flic_ctx_bytes_in_use(const flic_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return fail(FLIC_EINVAL, "null argument");
+    *bytes = ctx->used;
+    return FLIC_OK;
+}
+
 flic_status flic_ctx_set_pass_timing(flic_ctx* ctx, int32_t enable) {
     if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
     ctx->timing = enable != 0;
@@ -412,7 +444,7 @@ flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img, int32_t H,
     flic_status st = check_scan(range_img, H, W, alpha_tables, threshold, skip_depth, labels_out, 0);
     if (st != FLIC_OK) return st;
     const flic_scan s{range_img, H, W, *alpha_tables, threshold, skip_depth, labels_out};
-    const int tw = choose_tile_w(ctx, H, W);
+    const int tw = choose_tile_w(ctx, H, W, skip_depth);
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(set_device(ctx->device));
     flic_ctx::Slot* slot = nullptr;

@@ -69,6 +69,12 @@ def lib() -> ctypes.CDLL:
     L.flic_plan_destroy.restype = None
     L.flic_set_tile_override.argtypes = [vp, i32]
     L.flic_set_tile_override.restype = i32
+    L.flic_ctx_set_tile_rule.argtypes = [vp, i32, i32, i32, i32]
+    L.flic_ctx_set_tile_rule.restype = i32
+    L.flic_ctx_tile_for.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i32)]
+    L.flic_ctx_tile_for.restype = i32
+    L.flic_ctx_bytes_in_use.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.flic_ctx_bytes_in_use.restype = i32
     L.flic_ctx_set_pass_timing.argtypes = [vp, i32]
     L.flic_ctx_set_pass_timing.restype = i32
     L.flic_ctx_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32)]
@@ -192,6 +198,31 @@ class Context:
     def set_tile_width(self, tile_w: int) -> None:
         """0 restores the built-in choice."""
         _check(lib().flic_set_tile_override(self.handle, int(tile_w)))
+
+    def set_tile_rule(self, H: int, W: int, skip_depth: int, tile_w: int) -> None:
+        """Use tile_w columns per tile for scans of exactly this shape (0 removes)."""
+        _check(lib().flic_ctx_set_tile_rule(self.handle, int(H), int(W), int(skip_depth), int(tile_w)))
+
+    def tile_for(self, H: int, W: int, skip_depth: int) -> int:
+        out = ctypes.c_int32()
+        _check(lib().flic_ctx_tile_for(self.handle, int(H), int(W), int(skip_depth), ctypes.byref(out)))
+        return int(out.value)
+
+    def bytes_in_use(self) -> int:
+        out = ctypes.c_size_t()
+        _check(lib().flic_ctx_bytes_in_use(self.handle, ctypes.byref(out)))
+        return int(out.value)
+
+    def cluster_batched_structs(self, structs: Sequence[_Scan], stream=None) -> None:
+        """flic_cluster_batched on already marshalled flic_scan structs."""
+        arr = (_Scan * max(1, len(structs)))(*structs)
+        _check(lib().flic_cluster_batched(self.handle, arr, len(structs), _stream_handle(stream)))
+
+    def cluster_struct_async(self, sc: _Scan, stream=None) -> None:
+        """flic_cluster_async on one marshalled flic_scan struct."""
+        _check(lib().flic_cluster_async(self.handle, sc.range_img, sc.H, sc.W, ctypes.byref(sc.tables),
+                                        sc.threshold, sc.skip_depth, sc.labels_out,
+                                        _stream_handle(stream)))
 
     def set_pass_timing(self, enable: bool) -> None:
         _check(lib().flic_ctx_set_pass_timing(self.handle, int(bool(enable))))

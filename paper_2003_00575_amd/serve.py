@@ -1,0 +1,419 @@
+"""Serving loop: many simulated Lidar sensors, continuous batching on one GPU.
+
+Every sensor registers once: its angle tables and a small pool of frame slots
+(device range + label buffers, pinned host staging) stay resident, admitted
+against an HBM budget.  Frames arrive on their own schedule (Poisson arrivals
+at each sensor's rate).  A frame is admitted as soon as one of its sensor's
+slots is free (otherwise it waits, FIFO per sensor); whenever one of the
+launch streams is idle, every admitted frame not yet launched (oldest first,
+up to max_batch) goes out as one batched launch: host-to-device copies, one
+flic_cluster_batched call, device-to-host copy of the labels, an event.  Work
+from different streams overlaps on the device.  Latency is measured from a
+frame's arrival to its labels being on the host.
+
+The scheduling core is independent of the device (a backend object does the
+copies and launches), so its admission, FIFO and statistics logic is tested on
+the CPU with a fake backend and a fake clock.
+
+    python -m paper_2003_00575_amd.serve --seconds 60 --sensors 32
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import dataclasses
+import json
+import math
+import time
+from typing import Callable, Deque, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# Statistics
+# ---------------------------------------------------------------------------
+
+def order_stat(xs: Sequence[float], q: float) -> float:
+    """Exact order statistic: the smallest x with at least q of the sample <= x."""
+    if not xs:
+        return float("nan")
+    s = sorted(xs)
+    k = max(0, math.ceil(q * len(s)) - 1)
+    return s[k]
+
+
+@dataclasses.dataclass
+class FrameRecord:
+    sensor: int
+    frame: int
+    t_arrival: float
+    t_admit: float = math.nan
+    t_launch: float = math.nan
+    t_done: float = math.nan
+    batch: int = -1
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+# ---------------------------------------------------------------------------
+# Arrivals
+# ---------------------------------------------------------------------------
+
+def poisson_schedule(rates_hz: Sequence[float], seconds: float, seed: int,
+                     speedup: float = 1.0) -> List[Tuple[float, int, int]]:
+    """(time, sensor, frame index) sorted by time; exponential gaps at rate
+    rate * speedup per sensor."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s, f in enumerate(rates_hz):
+        t, i = 0.0, 0
+        lam = f * speedup
+        while True:
+            t += rng.exponential(1.0 / lam)
+            if t >= seconds:
+                break
+            out.append((t, s, i))
+            i += 1
+    out.sort()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Scheduling core
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SensorSpec:
+    sensor: int
+    H: int
+    W: int
+    skip_depth: int
+    threshold: float
+
+    @property
+    def frame_bytes(self) -> int:
+        return self.H * self.W * 8          # range in + labels out, on the device
+
+
+class BudgetError(RuntimeError):
+    pass
+
+
+class ServingCore:
+    """Admission, per-sensor FIFO, slot pools and continuous batching.
+
+    backend must provide:
+      sensor_bytes(spec) -> int                 resident bytes besides slots
+      register(spec, n_slots) -> None           allocate tables + slots
+      stage(sensor, slot, frame) -> None        frame data into the slot
+      launch(stream, [(sensor, slot)]) -> token enqueue copies + one launch
+      done(token) -> bool
+      scratch_bytes(max_batch_px) -> int        library scratch for a batch
+    """
+
+    def __init__(self, backend, hbm_budget: int, n_streams: int = 3, max_batch: int = 64,
+                 slots_per_sensor: int = 3, max_queue: int = 64,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.b = backend
+        self.budget = int(hbm_budget)
+        self.n_streams = n_streams
+        self.max_batch = max_batch
+        self.slots_per_sensor = slots_per_sensor
+        self.max_queue = max_queue
+        self.clock = clock
+        self.specs: Dict[int, SensorSpec] = {}
+        self.free_slots: Dict[int, List[int]] = {}
+        self.waiting: Dict[int, Deque[FrameRecord]] = {}
+        self.admitted: Deque[Tuple[FrameRecord, int]] = collections.deque()
+        self.inflight: List[Optional[Tuple[object, List[Tuple[FrameRecord, int]]]]] = [None] * n_streams
+        self.records: List[FrameRecord] = []
+        self.dropped = 0
+        self.batches = 0
+        self.reserved = 0
+
+    # -- registration / admission by HBM budget --------------------------------
+    def resident_bytes(self, spec: SensorSpec) -> int:
+        return self.b.sensor_bytes(spec) + self.slots_per_sensor * spec.frame_bytes
+
+    def scratch_reserve(self) -> int:
+        # the library's launch ring: one batch of the largest shapes per stream
+        if not self.specs:
+            return 0
+        biggest = max(s.H * s.W for s in self.specs.values())
+        return self.b.scratch_bytes(self.max_batch * biggest) * self.n_streams
+
+    def add_sensor(self, spec: SensorSpec) -> None:
+        need = self.resident_bytes(spec)
+        saved = dict(self.specs)
+        self.specs[spec.sensor] = spec
+        total = self.reserved + need + self.scratch_reserve()
+        if total > self.budget:
+            self.specs = saved
+            raise BudgetError(f"sensor {spec.sensor}: {total} bytes would exceed the "
+                              f"HBM budget of {self.budget}")
+        self.b.register(spec, self.slots_per_sensor)
+        self.reserved += need
+        self.free_slots[spec.sensor] = list(range(self.slots_per_sensor))
+        self.waiting[spec.sensor] = collections.deque()
+
+    # -- event handling -------------------------------------------------------------
+    def arrive(self, sensor: int, frame: int, t_arrival: float) -> None:
+        rec = FrameRecord(sensor, frame, t_arrival)
+        self.records.append(rec)
+        q = self.waiting[sensor]
+        if len(q) >= self.max_queue:
+            old = q.popleft()
+            old.t_done = math.inf
+            self.dropped += 1
+        q.append(rec)
+        self._admit(sensor)
+
+    def _admit(self, sensor: int) -> None:
+        q, slots = self.waiting[sensor], self.free_slots[sensor]
+        while q and slots:
+            rec = q.popleft()
+            slot = slots.pop()
+            self.b.stage(sensor, slot, rec.frame)
+            rec.t_admit = self.clock()
+            self.admitted.append((rec, slot))
+
+    def poll(self) -> int:
+        """Retire finished batches; returns how many frames completed."""
+        n = 0
+        for i, fl in enumerate(self.inflight):
+            if fl is None or not self.b.done(fl[0]):
+                continue
+            now = self.clock()
+            for rec, slot in fl[1]:
+                rec.t_done = now
+                self.free_slots[rec.sensor].append(slot)
+                n += 1
+            self.inflight[i] = None
+            for s in {rec.sensor for rec, _ in fl[1]}:
+                self._admit(s)
+        return n
+
+    def launch_ready(self) -> int:
+        """Launch admitted frames on every idle stream; returns frames launched."""
+        n = 0
+        for i in range(self.n_streams):
+            if self.inflight[i] is not None or not self.admitted:
+                continue
+            batch = [self.admitted.popleft() for _ in range(min(self.max_batch, len(self.admitted)))]
+            now = self.clock()
+            for rec, _ in batch:
+                rec.t_launch = now
+                rec.batch = self.batches
+            token = self.b.launch(i, [(rec.sensor, slot) for rec, slot in batch])
+            self.inflight[i] = (token, batch)
+            self.batches += 1
+            n += len(batch)
+        return n
+
+    def busy(self) -> bool:
+        return bool(self.admitted) or any(f is not None for f in self.inflight) or \
+            any(self.waiting[s] for s in self.waiting)
+
+    # -- driver ---------------------------------------------------------------------
+    def run(self, schedule: Sequence[Tuple[float, int, int]], drain: bool = True,
+            sleep: Callable[[float], None] = time.sleep) -> None:
+        """Feed arrivals at their scheduled times (relative to now)."""
+        t0 = self.clock()
+        i = 0
+        while i < len(schedule) or (drain and self.busy()):
+            now = self.clock() - t0
+            while i < len(schedule) and schedule[i][0] <= now:
+                t, s, f = schedule[i]
+                self.arrive(s, f, t0 + t)
+                i += 1
+            self.poll()
+            self.launch_ready()
+            idle = not self.admitted and all(f is None for f in self.inflight)
+            if idle and i < len(schedule):
+                wait = schedule[i][0] - (self.clock() - t0)
+                if wait > 2e-4:
+                    sleep(min(wait, 1e-3))
+
+    def stats(self, warmup_s: float = 0.0, t0: Optional[float] = None) -> dict:
+        done = [r for r in self.records if math.isfinite(r.t_done)]
+        if t0 is None:
+            t0 = min((r.t_arrival for r in self.records), default=0.0)
+        kept = [r for r in done if r.t_arrival - t0 >= warmup_s]
+        lat = [r.latency * 1e3 for r in kept]
+        span = (max(r.t_done for r in kept) - min(r.t_arrival for r in kept)) if kept else math.nan
+        px = sum(self.specs[r.sensor].H * self.specs[r.sensor].W for r in kept)
+        return {"frames": len(kept), "dropped": self.dropped, "batches": self.batches,
+                "p50_ms": order_stat(lat, 0.50), "p99_ms": order_stat(lat, 0.99),
+                "max_ms": max(lat) if lat else math.nan,
+                "scans_per_s": len(kept) / span if kept and span > 0 else math.nan,
+                "gpix_per_s": px / span / 1e9 if kept and span > 0 else math.nan,
+                "mean_batch": (len(done) / self.batches) if self.batches else 0.0}
+
+
+# ---------------------------------------------------------------------------
+# GPU backend
+# ---------------------------------------------------------------------------
+
+class GpuBackend:
+    """Device side of the serving loop: resident tables and frame slots,
+    copies on the launch streams, batched (or per-scan) launches."""
+
+    def __init__(self, ctx, frames: Dict[int, List[np.ndarray]], tables: Dict[int, tuple],
+                 n_streams: int, batched: bool = True, keep_labels: bool = False):
+        import torch
+        from . import flic
+        self.torch, self.flic = torch, flic
+        self.ctx = ctx
+        self.frames = frames
+        self.tables = tables
+        self.batched = batched
+        self.keep_labels = keep_labels
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.slots: Dict[Tuple[int, int], dict] = {}
+        self.dev_tables: Dict[int, tuple] = {}
+        self.specs: Dict[int, SensorSpec] = {}
+        self.results: Dict[Tuple[int, int], np.ndarray] = {}
+
+    def sensor_bytes(self, spec: SensorSpec) -> int:
+        cv, ch = self.tables[spec.sensor]
+        return cv.nbytes + ch.nbytes
+
+    def scratch_bytes(self, px: int) -> int:
+        return px * 5                      # parent array + masks + border arrays, generous
+
+    def register(self, spec: SensorSpec, n_slots: int) -> None:
+        torch = self.torch
+        cv, ch = self.tables[spec.sensor]
+        dcv = torch.from_numpy(cv).cuda()
+        dch = torch.from_numpy(ch).cuda()
+        self.dev_tables[spec.sensor] = (dcv, dch)
+        self.specs[spec.sensor] = spec
+        for k in range(n_slots):
+            rng_d = torch.empty((spec.H, spec.W), dtype=torch.float32, device="cuda")
+            lab_d = torch.empty((spec.H, spec.W), dtype=torch.int32, device="cuda")
+            st = self.flic._Scan(rng_d.data_ptr(), spec.H, spec.W,
+                                 self.flic._Tables(dcv.data_ptr(), dch.data_ptr()),
+                                 float(spec.threshold), int(spec.skip_depth), lab_d.data_ptr())
+            self.slots[(spec.sensor, k)] = {
+                "range": rng_d, "labels": lab_d, "struct": st,
+                "h_in": torch.empty((spec.H, spec.W), dtype=torch.float32, pin_memory=True),
+                "h_out": torch.empty((spec.H, spec.W), dtype=torch.int32, pin_memory=True),
+                "frame": -1}
+
+    def stage(self, sensor: int, slot: int, frame: int) -> None:
+        sl = self.slots[(sensor, slot)]
+        pool = self.frames[sensor]
+        sl["h_in"].numpy()[...] = pool[frame % len(pool)]
+        sl["frame"] = frame
+
+    def launch(self, stream: int, items: Sequence[Tuple[int, int]]):
+        torch = self.torch
+        st = self.streams[stream]
+        with torch.cuda.stream(st):
+            for key in items:
+                sl = self.slots[key]
+                sl["range"].copy_(sl["h_in"], non_blocking=True)
+            if self.batched:
+                self.ctx.cluster_batched_structs([self.slots[k]["struct"] for k in items], st)
+            else:
+                for key in items:
+                    self.ctx.cluster_struct_async(self.slots[key]["struct"], st)
+            for key in items:
+                sl = self.slots[key]
+                sl["h_out"].copy_(sl["labels"], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return (ev, list(items))
+
+    def done(self, token) -> bool:
+        ev, items = token
+        if not ev.query():
+            return False
+        if self.keep_labels:
+            for key in items:
+                sl = self.slots[key]
+                self.results[(key[0], sl["frame"])] = sl["h_out"].numpy().copy()
+        return True
+
+
+# ---------------------------------------------------------------------------
+# Workload and runner
+# ---------------------------------------------------------------------------
+
+def make_fleet(n_sensors: int, pool: int, seed: int = 0):
+    """Sensor s uses the mixed shape s mod 5; rate U(10, 20) Hz; threshold
+    U{0.3, 0.5, 0.8, 1.0}; skip depth 3; a pool of raycast frames."""
+    from . import synth
+    rng = np.random.default_rng(seed)
+    specs, frames, tables, rates = [], {}, {}, []
+    for s in range(n_sensors):
+        H, W, _, _ = synth.MIXED_SHAPES[s % 5]
+        T = float(rng.choice([0.3, 0.5, 0.8, 1.0]))
+        rates.append(float(rng.uniform(10.0, 20.0)))
+        specs.append(SensorSpec(s, H, W, 3, T))
+        scans = [synth.sensor_frame(s, f, T) for f in range(pool)]
+        frames[s] = [sc.range_img for sc in scans]
+        tables[s] = (scans[0].cos_v, scans[0].cos_h)
+    return specs, frames, tables, rates
+
+
+def serve_once(specs, frames, tables, rates, seconds: float, speedup: float, batched: bool,
+               n_streams: int, budget: int, seed: int = 1, warmup_s: float = 1.0,
+               max_batch: int = 64, keep_labels: bool = False):
+    import torch
+    from . import flic
+    ctx = flic.Context(0)
+    be = GpuBackend(ctx, frames, tables, n_streams, batched=batched, keep_labels=keep_labels)
+    core = ServingCore(be, budget, n_streams=n_streams, max_batch=max_batch if batched else 1)
+    for sp in specs:
+        core.add_sensor(sp)
+    # warm the launch paths before the clock starts
+    warm = [(0.0, sp.sensor, 0) for sp in specs]
+    core.run(warm)
+    torch.cuda.synchronize()
+    core.records.clear()
+    core.dropped = 0
+    core.batches = 0
+    sched = poisson_schedule(rates, seconds, seed, speedup)
+    t0 = time.perf_counter()
+    core.run(sched)
+    torch.cuda.synchronize()
+    st = core.stats(warmup_s=warmup_s, t0=t0)
+    st.update({"mode": "batched" if batched else "per-scan", "speedup": speedup,
+               "streams": n_streams, "offered_scans_per_s": sum(rates) * speedup,
+               "hbm_reserved_bytes": core.reserved, "ctx_bytes": ctx.bytes_in_use()})
+    return st, be, core
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--sensors", type=int, default=32)
+    ap.add_argument("--seconds", type=float, default=60.0)
+    ap.add_argument("--warmup", type=float, default=2.0)
+    ap.add_argument("--pool", type=int, default=16, help="frames generated per sensor")
+    ap.add_argument("--speedups", default="1,4,16", help="time-compression factors to sweep")
+    ap.add_argument("--streams", type=int, default=3)
+    ap.add_argument("--budget-gb", type=float, default=4.0)
+    ap.add_argument("--p99-ms", type=float, default=10.0)
+    args = ap.parse_args()
+    specs, frames, tables, rates = make_fleet(args.sensors, args.pool)
+    out = []
+    for m in [float(x) for x in args.speedups.split(",")]:
+        for batched in (True, False):
+            st, _, _ = serve_once(specs, frames, tables, rates, args.seconds, m, batched,
+                                  args.streams, int(args.budget_gb * 2**30), warmup_s=args.warmup)
+            out.append(st)
+            print(json.dumps(st), flush=True)
+    for mode in ("batched", "per-scan"):
+        ok = [s for s in out if s["mode"] == mode and s["p99_ms"] <= args.p99_ms and s["dropped"] == 0]
+        best = max(ok, key=lambda s: s["scans_per_s"]) if ok else None
+        print(json.dumps({"mode": mode, "p99_limit_ms": args.p99_ms,
+                          "max_scans_per_s_at_p99": best["scans_per_s"] if best else None}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

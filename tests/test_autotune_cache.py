@@ -1,0 +1,22 @@
+"""Autotuner bookkeeping on the CPU: choice rule, cache format, round trip."""
+from paper_2003_00575_amd import autotune
+
+
+def test_best_choice_prefers_fastest_then_wider():
+    assert autotune.best_choice({64: 3.0, 128: 2.0, 256: 2.5}) == 128
+    assert autotune.best_choice({64: 2.0, 128: 2.0, 256: 2.0}) == 256
+
+
+def test_cache_round_trip(tmp_path):
+    cache = {}
+    autotune.record(cache, "gfx950", (128, 2048, 3), {64: 1.0, 128: 1.5, 256: 2.0})
+    autotune.record(cache, "gfx950", (16, 1024, 3), {64: 3.0, 128: 2.0, 256: 1.0})
+    autotune.record(cache, "gfx942", (16, 1024, 3), {64: 1.0, 128: 2.0, 256: 3.0})
+    p = str(tmp_path / "t.json")
+    autotune.save_cache(p, cache)
+    back = autotune.load_cache(p)
+    assert back == cache
+    assert autotune.rules_for(back, "gfx950") == [(128, 2048, 3, 64), (16, 1024, 3, 256)]
+    assert autotune.rules_for(back, "gfx942") == [(16, 1024, 3, 64)]
+    assert autotune.parse_key(autotune.shape_key(32, 1800, 5)) == (32, 1800, 5)
+    assert autotune.load_cache(str(tmp_path / "missing.json")) == {}

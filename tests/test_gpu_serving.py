@@ -1,0 +1,95 @@
+"""Serving loop and autotuner on the GPU.
+
+Alone vs in the mix: every frame served by the continuous-batching loop (many
+sensors, mixed shapes, overlapping streams) must carry exactly the labels the
+oracle gives for that frame alone, and the labels the plain per-scan path
+gives.  The autotuner's tile rules change speed only, never labels."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_00575_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def flic():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_00575_amd import flic as f
+    f.lib()
+    return f
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_served_frames_equal_alone(flic, batched):
+    from paper_2003_00575_amd import serve
+    specs, frames, tables, rates = serve.make_fleet(10, pool=3, seed=5)
+    st, be, core = serve.serve_once(specs, frames, tables, rates, seconds=0.4, speedup=4.0,
+                                    batched=batched, n_streams=3, budget=4 << 30,
+                                    warmup_s=0.0, keep_labels=True)
+    assert st["frames"] > 20 and st["dropped"] == 0
+    if batched:
+        assert st["mean_batch"] > 1.0
+    checked = 0
+    for (sensor, frame), got in sorted(be.results.items()):
+        sp = specs[sensor]
+        pool = frames[sensor]
+        img = pool[frame % len(pool)]
+        cv, ch = tables[sensor]
+        want = oracle.cluster(img, cv, ch, sp.threshold, sp.skip_depth)
+        assert np.array_equal(got, want), (sensor, frame)
+        checked += 1
+    assert checked >= 10
+    # the plain per-scan path on one frame per sensor
+    ctx = flic.Context(0)
+    for sp in specs[:5]:
+        d = flic.DeviceScan(torch.from_numpy(frames[sp.sensor][0]).cuda(),
+                            torch.from_numpy(tables[sp.sensor][0]).cuda(),
+                            torch.from_numpy(tables[sp.sensor][1]).cuda(), sp.threshold, sp.skip_depth)
+        ctx.cluster_async(d)
+        torch.cuda.synchronize()
+        want = oracle.cluster(frames[sp.sensor][0], *tables[sp.sensor], sp.threshold, sp.skip_depth)
+        assert np.array_equal(d.labels.cpu().numpy(), want)
+
+
+def test_budget_admission_on_device(flic):
+    from paper_2003_00575_amd import serve
+    specs, frames, tables, rates = serve.make_fleet(6, pool=1, seed=2)
+    ctx = flic.Context(0)
+    be = serve.GpuBackend(ctx, frames, tables, n_streams=2)
+    probe = serve.ServingCore(be, 1 << 40, n_streams=2, max_batch=4)
+    two = sum(probe.resident_bytes(s) for s in specs[:2])
+    biggest = max(s.H * s.W for s in specs[:2])
+    core = serve.ServingCore(be, two + be.scratch_bytes(4 * biggest) * 2, n_streams=2, max_batch=4)
+    core.add_sensor(specs[0])
+    core.add_sensor(specs[1])
+    with pytest.raises(serve.BudgetError):
+        core.add_sensor(specs[2])             # a bigger sensor no longer fits
+    assert sorted(core.specs) == [0, 1]
+
+
+def test_autotune_rules_keep_labels(flic, tmp_path):
+    from paper_2003_00575_amd import autotune
+    ctx = flic.Context(0)
+    shape = (64, 2048, 3)
+    timings = autotune.time_shape(ctx, shape, n_scans=4, reps=2)
+    assert set(timings) == set(autotune.CANDIDATES) and all(v > 0 for v in timings.values())
+    cache = {}
+    choice = autotune.record(cache, autotune.gpu_arch(), shape, timings)
+    path = str(tmp_path / "tiles.json")
+    autotune.save_cache(path, cache)
+    again = autotune.load_cache(path)
+    assert autotune.apply(ctx, again, autotune.gpu_arch()) == 1
+    assert ctx.tile_for(*shape) == choice
+    scan = synth.single_scan()
+    want = oracle.cluster_scan(scan)
+    for tw in autotune.CANDIDATES:
+        ctx.set_tile_rule(64, 2048, 3, tw)
+        assert ctx.tile_for(64, 2048, 3) == tw
+        d = flic.to_device(scan)
+        ctx.cluster_async(d)
+        torch.cuda.synchronize()
+        assert np.array_equal(d.labels.cpu().numpy(), want), tw
