@@ -40,6 +40,64 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def uneven_batch(ctx, flic, synth, torch, dev, stream, n=256, reps=10):
+    """256 scans of mixed shapes (16x1024 .. 128x4096, own tables and
+    thresholds): one hipGraph plan launch vs 256 per-scan launches."""
+    t0 = time.time()
+    host = [synth.mixed_scan(i) for i in range(n)]
+    print(f"[bench] generated {n} mixed scans in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    devs = [flic.to_device(s, dev) for s in host]
+    px = sum(s.H * s.W for s in host)
+    plan = ctx.plan(devs)
+    for _ in range(3):
+        plan.relaunch(stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        plan.relaunch(stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    plan_ms = a.elapsed_time(b) / reps
+    structs = [d.to_c() for d in devs]
+    for sc in structs:
+        ctx.cluster_struct_async(sc, stream)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        for sc in structs:
+            ctx.cluster_struct_async(sc, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    single_ms = a.elapsed_time(b) / reps
+    plan.close()
+    return {"workload": f"{n} scans, shapes 16x1024/32x1800/64x2048/128x2048/128x4096 round robin, "
+                        f"own tables and thresholds, skip 3", "pixels": px,
+            "plan_ms": round(plan_ms, 4), "per_scan_launches_ms": round(single_ms, 4),
+            "plan_gpix_s": round(px / (plan_ms * 1e-3) / 1e9, 3),
+            "per_scan_gpix_s": round(px / (single_ms * 1e-3) / 1e9, 3),
+            "plan_scans_s": round(n / (plan_ms * 1e-3), 1),
+            "per_scan_scans_s": round(n / (single_ms * 1e-3), 1)}
+
+
+def serving_excerpt(seconds, speedups=(4.0, 16.0), sensors=32):
+    """Continuous batching vs per-scan launches for 32 simulated sensors."""
+    from paper_2003_00575_amd import serve
+    specs, frames, tables, rates = serve.make_fleet(sensors, pool=4)
+    out = []
+    for m in speedups:
+        for batched in (True, False):
+            st, _, _ = serve.serve_once(specs, frames, tables, rates, seconds, m, batched,
+                                        n_streams=3, budget=4 << 30, warmup_s=0.5)
+            out.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()
+                        if k in ("mode", "speedup", "offered_scans_per_s", "scans_per_s", "p50_ms",
+                                 "p99_ms", "frames", "dropped", "mean_batch")})
+            print(f"[bench] serving x{m} {out[-1]['mode']}: p50 {out[-1]['p50_ms']} ms, "
+                  f"p99 {out[-1]['p99_ms']} ms", file=sys.stderr, flush=True)
+    return {"workload": f"{sensors} sensors (mixed shapes, 10-20 Hz Poisson, time-compressed), "
+                        f"{seconds} s per run, 4 GB HBM budget, 3 streams", "runs": out}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +110,9 @@ def main() -> int:
     ap.add_argument("--tile-w", type=int, default=0, help="force a tile width (0 = built-in)")
     ap.add_argument("--streams", type=int, default=3,
                     help="1: all launches on one stream; 3: one stream per threshold")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 256-scan mixed batch")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving excerpt")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed batch and the per-kernel timing (for profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -91,7 +152,9 @@ def main() -> int:
         return [flic.DeviceScan(ranges[s][i], cos_v[i], cos_h[i], THRESHOLDS[ti], SKIP, labels[s][ti][i])
                 for i in range(N_SCANS)]
 
+    from paper_2003_00575_amd import autotune
     ctx = flic.Context(0)
+    autotune.apply_default(ctx)
     if args.tile_w:
         ctx.set_tile_width(args.tile_w)
     plans = {(s, ti): ctx.plan(scans_for(s, ti)) for s in range(S) for ti in range(len(THRESHOLDS))}
@@ -214,6 +277,9 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    uneven = None if args.no_uneven else uneven_batch(ctx, flic, synth, torch, dev, stream)
+    serving = None if args.no_serve else serving_excerpt(args.serve_seconds)
+
     # ---- CPU oracle on a bounded sample -------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -263,6 +329,8 @@ def main() -> int:
                        "host_p99": round(percentile(lat_host, 0.99), 4),
                        "device_p50": round(percentile(lat_dev, 0.5), 4),
                        "device_p99": round(percentile(lat_dev, 0.99), 4)},
+        "uneven_batch": uneven,
+        "serving": serving,
         "cpu_baseline": cpu,
         "paper_context": "165 Hz (Python, one i7-6820HQ core, 64-beam scans; Section IV.A)",
     }

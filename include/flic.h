@@ -147,6 +147,17 @@ flic_status flic_ctx_set_tile_rule(flic_ctx* ctx, int32_t H, int32_t W, int32_t 
 flic_status flic_ctx_tile_for(const flic_ctx* ctx, int32_t H, int32_t W, int32_t skip_depth,
                               int32_t* tile_w);
 
+/* Descriptor and scratch bytes a flic_cluster_batched call on `scans` would
+ * need (only the shapes, skip depths and tile rules matter; pointers are
+ * checked like a launch's but never dereferenced).                        */
+flic_status flic_batch_bytes(const flic_ctx* ctx, const flic_scan* scans, int32_t n,
+                             size_t* desc_bytes, size_t* scratch_bytes);
+
+/* Grow every launch slot of the context to at least these sizes now (within
+ * its HBM budget), so later launches never allocate or free device memory.
+ * Waits for the slots' previous launches.                                   */
+flic_status flic_ctx_reserve(flic_ctx* ctx, size_t desc_bytes, size_t scratch_bytes);
+
 /* Device bytes the context and its plans currently hold (descriptor and
  * scratch buffers); the budget given to flic_ctx_create caps this value.   */
 flic_status flic_ctx_bytes_in_use(const flic_ctx* ctx, size_t* bytes);

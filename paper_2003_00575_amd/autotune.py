@@ -74,6 +74,14 @@ def apply(ctx, cache: Dict[str, Dict[str, dict]], arch: str) -> int:
     return len(rules)
 
 
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles.json")
+
+
+def apply_default(ctx) -> int:
+    """Install the shipped tile table for this GPU (if it has an entry)."""
+    return apply(ctx, load_cache(DEFAULT_CACHE), gpu_arch())
+
+
 def gpu_arch() -> str:
     import torch
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]

@@ -408,6 +408,29 @@ flic_status flic_ctx_tile_for(const flic_ctx* ctx, int32_t H, int32_t W, int32_t
     return FLIC_OK;
 }
 
+flic_status flic_batch_bytes(const flic_ctx* ctx, const flic_scan* scans, int32_t n,
+                             size_t* desc_bytes, size_t* scratch) {
+    if (!ctx || !desc_bytes || !scratch) return fail(FLIC_EINVAL, "null argument");
+    flic_status st = check_scans(scans, n);
+    if (st != FLIC_OK) return st;
+    Layout L;
+    build_layout(ctx, scans, n, nullptr, L);
+    *desc_bytes = L.blob.size();
+    *scratch = scratch_bytes(ctx, scans, n);
+    return FLIC_OK;
+}
+
+flic_status flic_ctx_reserve(flic_ctx* ctx, size_t desc_bytes, size_t scratch) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    HIP_TRY(set_device(ctx->device));
+    for (int i = 0; i < flic_ctx::kRing; ++i) {
+        flic_ctx::Slot* slot = nullptr;
+        flic_status st = acquire_slot(ctx, desc_bytes, scratch, &slot);
+        if (st != FLIC_OK) return st;
+    }
+    return FLIC_OK;
+}
+
 flic_status flic_ctx_bytes_in_use(const flic_ctx* ctx, size_t* bytes) {
     if (!ctx || !bytes) return fail(FLIC_EINVAL, "null argument");
     *bytes = ctx->used;

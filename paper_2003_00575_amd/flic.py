@@ -73,6 +73,11 @@ def lib() -> ctypes.CDLL:
     L.flic_ctx_set_tile_rule.restype = i32
     L.flic_ctx_tile_for.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i32)]
     L.flic_ctx_tile_for.restype = i32
+    L.flic_batch_bytes.argtypes = [vp, ctypes.POINTER(_Scan), i32, ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_size_t)]
+    L.flic_batch_bytes.restype = i32
+    L.flic_ctx_reserve.argtypes = [vp, ctypes.c_size_t, ctypes.c_size_t]
+    L.flic_ctx_reserve.restype = i32
     L.flic_ctx_bytes_in_use.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.flic_ctx_bytes_in_use.restype = i32
     L.flic_ctx_set_pass_timing.argtypes = [vp, i32]
@@ -207,6 +212,17 @@ class Context:
         out = ctypes.c_int32()
         _check(lib().flic_ctx_tile_for(self.handle, int(H), int(W), int(skip_depth), ctypes.byref(out)))
         return int(out.value)
+
+    def batch_bytes(self, structs: Sequence[_Scan]):
+        """(descriptor bytes, scratch bytes) a batched launch of these scans needs."""
+        arr = (_Scan * max(1, len(structs)))(*structs)
+        db, sb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().flic_batch_bytes(self.handle, arr, len(structs), ctypes.byref(db), ctypes.byref(sb)))
+        return int(db.value), int(sb.value)
+
+    def reserve(self, desc_bytes: int, scratch_bytes: int) -> None:
+        """Pre-size every launch slot (no allocation during later launches)."""
+        _check(lib().flic_ctx_reserve(self.handle, int(desc_bytes), int(scratch_bytes)))
 
     def bytes_in_use(self) -> int:
         out = ctypes.c_size_t()

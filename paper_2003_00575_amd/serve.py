@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import collections
 import dataclasses
+import gc
 import json
 import math
 import time
@@ -143,7 +144,8 @@ class ServingCore:
         if not self.specs:
             return 0
         biggest = max(s.H * s.W for s in self.specs.values())
-        return self.b.scratch_bytes(self.max_batch * biggest) * self.n_streams
+        slots = getattr(self.b, "ring_slots", self.n_streams)
+        return self.b.scratch_bytes(self.max_batch * biggest) * slots
 
     def add_sensor(self, spec: SensorSpec) -> None:
         need = self.resident_bytes(spec)
@@ -261,6 +263,8 @@ class GpuBackend:
     """Device side of the serving loop: resident tables and frame slots,
     copies on the launch streams, batched (or per-scan) launches."""
 
+    ring_slots = 4                         # launch slots of a flic context
+
     def __init__(self, ctx, frames: Dict[int, List[np.ndarray]], tables: Dict[int, tuple],
                  n_streams: int, batched: bool = True, keep_labels: bool = False):
         import torch
@@ -283,6 +287,16 @@ class GpuBackend:
 
     def scratch_bytes(self, px: int) -> int:
         return px * 5                      # parent array + masks + border arrays, generous
+
+    def reserve(self, max_batch: int) -> None:
+        """Size the library's launch slots for the largest possible batch now,
+        so no launch allocates (or frees, which synchronises the device)."""
+        biggest = max(self.specs.values(), key=lambda s: s.H * s.W)
+        st = self.slots[(biggest.sensor, 0)]["struct"]
+        desc, scratch = self.ctx.batch_bytes([st])
+        n = max(1, max_batch)
+        # descriptors + block map grow with the tile count; scratch with pixels
+        self.ctx.reserve(desc * n, scratch * n)
 
     def register(self, spec: SensorSpec, n_slots: int) -> None:
         torch = self.torch
@@ -365,11 +379,14 @@ def serve_once(specs, frames, tables, rates, seconds: float, speedup: float, bat
                max_batch: int = 64, keep_labels: bool = False):
     import torch
     from . import flic
+    from . import autotune
     ctx = flic.Context(0)
+    autotune.apply_default(ctx)
     be = GpuBackend(ctx, frames, tables, n_streams, batched=batched, keep_labels=keep_labels)
     core = ServingCore(be, budget, n_streams=n_streams, max_batch=max_batch if batched else 1)
     for sp in specs:
         core.add_sensor(sp)
+    be.reserve(max_batch if batched else 1)
     # warm the launch paths before the clock starts
     warm = [(0.0, sp.sensor, 0) for sp in specs]
     core.run(warm)
@@ -378,9 +395,15 @@ def serve_once(specs, frames, tables, rates, seconds: float, speedup: float, bat
     core.dropped = 0
     core.batches = 0
     sched = poisson_schedule(rates, seconds, seed, speedup)
-    t0 = time.perf_counter()
-    core.run(sched)
-    torch.cuda.synchronize()
+    gc_was = gc.isenabled()
+    gc.disable()                      # no collector pauses inside the timed loop
+    try:
+        t0 = time.perf_counter()
+        core.run(sched)
+        torch.cuda.synchronize()
+    finally:
+        if gc_was:
+            gc.enable()
     st = core.stats(warmup_s=warmup_s, t0=t0)
     st.update({"mode": "batched" if batched else "per-scan", "speedup": speedup,
                "streams": n_streams, "offered_scans_per_s": sum(rates) * speedup,

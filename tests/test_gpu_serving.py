@@ -63,7 +63,8 @@ def test_budget_admission_on_device(flic):
     probe = serve.ServingCore(be, 1 << 40, n_streams=2, max_batch=4)
     two = sum(probe.resident_bytes(s) for s in specs[:2])
     biggest = max(s.H * s.W for s in specs[:2])
-    core = serve.ServingCore(be, two + be.scratch_bytes(4 * biggest) * 2, n_streams=2, max_batch=4)
+    core = serve.ServingCore(be, two + be.scratch_bytes(4 * biggest) * be.ring_slots, n_streams=2,
+                             max_batch=4)
     core.add_sensor(specs[0])
     core.add_sensor(specs[1])
     with pytest.raises(serve.BudgetError):
