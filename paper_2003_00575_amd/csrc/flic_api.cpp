@@ -191,6 +191,7 @@ ScanDesc make_desc(const flic_scan& s, int tile_w, int32_t tile_begin, char* scr
     d.bcol_r = reinterpret_cast<int32_t*>(scratch + S.bcol_r);
     d.brow_v = reinterpret_cast<float*>(scratch + S.brow_v);
     d.brow_r = reinterpret_cast<int32_t*>(scratch + S.brow_r);
+    d.flags = reinterpret_cast<int32_t*>(scratch + S.flags);
     return d;
 }
 

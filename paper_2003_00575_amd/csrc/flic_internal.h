@@ -26,6 +26,8 @@ constexpr int kMaxSkip = 8;
 //           first (side 0) and last (side 1) N columns of each tile.
 //   brow_v / brow_r  [tiles][2][N][tile_w]: the same for the first and last N
 //           rows; present only when the scan has more than one tile row.
+//   flags   one int32 written by pass 2: nonzero when some root pair was
+//           joined outside the compressed set, so pass 3 must walk to roots.
 // Between passes 1 and 3 the label array holds, at the start of each row
 // chunk, the global root of every run of that chunk in order.
 struct ScanDesc {
@@ -39,6 +41,7 @@ struct ScanDesc {
     int32_t* bcol_r;
     float* brow_v;
     int32_t* brow_r;
+    int32_t* flags;
     int32_t H, W, N;
     float t2;               // fl32(T*T)
     int32_t tile_w;         // tile columns
@@ -61,7 +64,7 @@ inline int tile_h_for(int tile_w) { return kTilePx / tile_w; }
 // Scratch bytes one scan needs, and the sub-buffer offsets (each 256-byte
 // aligned) relative to the scan's scratch base.
 struct ScratchLayout {
-    size_t masks, parent, bcol_v, bcol_r, brow_v, brow_r, total;
+    size_t masks, parent, bcol_v, bcol_r, brow_v, brow_r, flags, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -78,6 +81,7 @@ inline ScratchLayout scratch_layout(int H, int W, int N, int tile_w) {
     L.bcol_r = o; o = align256(o + tiles * 2 * N * tile_h * 4);
     L.brow_v = o; o = align256(o + (rows ? tiles * 2 * N * tile_w * 4 : 0));
     L.brow_r = o; o = align256(o + (rows ? tiles * 2 * N * tile_w * 4 : 0));
+    L.flags = o;  o = align256(o + 4);
     L.total = o;
     return L;
 }

@@ -248,12 +248,16 @@ void k_tile_label(BatchRef ref) {
             if (k >= 2) vneed &= ~chain;
             if (lane_bit(vneed)) t |= 1u << k;
         }
-        todo[j] = t;
         const bool valid = a == a;
         const int head = 63 - __clzll(~(h1 << 1) & le);   // first pixel of the run
         par[r * TW + c] = valid ? r * TW + ch * 64 + head : -1;
         if (valid && head == lane) heads |= 1u << j;
         if (valid) valids |= 1u << j;
+        // materialise this row's per-lane results here: otherwise the compiler
+        // sinks them to their uses after the barrier and keeps the 64-bit
+        // masks alive (spilled) instead
+        asm volatile("" : "+v"(t), "+v"(heads), "+v"(valids));
+        todo[j] = t;
 #pragma unroll
         for (int k = N - 1; k >= 1; --k) {
             wv[k] = wv[k - 1];
@@ -406,7 +410,7 @@ __device__ void wg_unite(int* par, int a, int b) {
 // (open addressing, 64-bit compare-and-swap), so each distinct pair is joined
 // once.  A pair that finds no slot within kMaxProbe probes is joined at once.
 __device__ __forceinline__ void push_pairs(bool act, int a, int b, unsigned long long* set,
-                                           int* par) {
+                                           int* par, int* overflow) {
     if (!act) return;
     const unsigned long long key = ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
     unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 40) & (kSetCap - 1);
@@ -416,6 +420,7 @@ __device__ __forceinline__ void push_pairs(bool act, int a, int b, unsigned long
         h = (h + 1) & (kSetCap - 1);
     }
     wg_unite(par, a, b);
+    *overflow = 1;
 }
 
 template <int TW, int N>
@@ -423,6 +428,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
     constexpr int kWaves = kMergeThreads / 64;
     __shared__ unsigned long long set[kSetCap];
+    __shared__ int overflow;
 
     const ScanDesc d = ref.descs ? ref.descs[blockIdx.x] : ref.one;
     const int W = d.W, H = d.H;
@@ -430,6 +436,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int* par = d.parent;
     for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) set[i] = kEmpty;
+    if (threadIdx.x == 0) overflow = 0;
     __syncthreads();
 
     // tile column borders: item = (tile, 64-row chunk); the tile's last N
@@ -489,7 +496,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
                 const uint64_t E = ballot(e);
                 const uint64_t V = ballot(us[j] && ut[m]);
                 const bool need = lane_bit(E & ~((E << 1) & V));
-                push_pairs(need, rsrc[j], rtgt[m], set, par);
+                push_pairs(need, rsrc[j], rtgt[m], set, par, &overflow);
             }
         }
     }
@@ -545,7 +552,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
                     const uint64_t E = ballot(e);
                     const uint64_t L = ballot(ls[j] && lt[m]);
                     const bool need = lane_bit(E & ~((E << 1) & L));
-                    push_pairs(need, rsrc[j], rtgt[m], set, par);
+                    push_pairs(need, rsrc[j], rtgt[m], set, par, &overflow);
                 }
             }
         }
@@ -565,6 +572,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
         if (ra != a) par[a] = ra;
         if (ra != b) par[b] = ra;
     }
+    if (threadIdx.x == 0) *d.flags = overflow;
 }
 
 // ---- pass 3: run lists -> labels ---------------------------------------------
@@ -605,7 +613,7 @@ __global__ __launch_bounds__(kLabelThreads) void k_relabel(BatchRef ref) {
     for (int j = 0; j < kRowsPerWave; ++j) {
         const bool row_in = j < rows;
         m[j] = row_in ? mrow[(size_t)j * d.chunks_per_row] : make_ulonglong2(0, 0);
-        listed[j] = (row_in && col_in && lane < __popcll(m[j].x)) ? seg0[(size_t)j * W + lane] : -1;
+        listed[j] = (row_in && col_in) ? seg0[(size_t)j * W + lane] : -1;
     }
     // ... then every pixel's run root and its final root ...
     int out[kRowsPerWave];
@@ -615,9 +623,11 @@ __global__ __launch_bounds__(kLabelThreads) void k_relabel(BatchRef ref) {
         const int groot = __shfl(listed[j], run < 0 ? 0 : run);
         out[j] = lane_bit(m[j].y) ? d.parent[groot] : -1;
     }
+    if (*d.flags) {                                  // some roots were joined uncompressed
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j)
-        if (lane_bit(m[j].y) && out[j] != d.parent[out[j]]) out[j] = root_of(d.parent, out[j]);
+        for (int j = 0; j < kRowsPerWave; ++j)
+            if (lane_bit(m[j].y)) out[j] = root_of(d.parent, out[j]);
+    }
     // ... then the labels (the run lists are overwritten only now)
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j)
