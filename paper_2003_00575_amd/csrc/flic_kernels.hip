@@ -89,24 +89,39 @@ __device__ __forceinline__ int lds_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Find with path halving (each visited node re-pointed at its grandparent),
+// which keeps the trees that concurrent joins build shallow for later finds.  atomicMin only ever moves a parent to an
+// ancestor (a smaller index of the same tree), so it is safe next to hooks.
 __device__ __forceinline__ int lds_find(int* par, int x) {
     int p = lds_load(&par[x]);
     while (p != x) {
-        x = p;
+        const int g = lds_load(&par[p]);
+        if (g == p) return p;
+        __hip_atomic_fetch_min(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = g;
         p = lds_load(&par[x]);
     }
     return x;
 }
 
+// Join the trees of a and b: the larger root is hooked under the smaller, so
+// every root is the smallest index of its tree.  Both ends are first walked to
+// their roots side by side (two loads in flight per step).
 __device__ void lds_unite(int* par, int a, int b) {
+    int pa = lds_load(&par[a]), pb = lds_load(&par[b]);
+    while (pa != a || pb != b) {
+        a = pa;
+        b = pb;
+        pa = lds_load(&par[a]);
+        pb = lds_load(&par[b]);
+    }
     for (;;) {
-        a = lds_find(par, a);
-        b = lds_find(par, b);
         if (a == b) return;
         if (a > b) { int t = a; a = b; b = t; }
         const int old = atomicMin(&par[b], a);
         if (old == b) return;
-        b = old;
+        a = lds_find(par, a);
+        b = lds_find(par, old);
     }
 }
 
