@@ -68,6 +68,17 @@ __device__ __forceinline__ float measurement_or_nan(float r) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Descriptor pointers are generic; viewed as global pointers, and indexed
+// with 32-bit offsets (every per-scan offset is below H*W <= INT32_MAX), the
+// accesses become global loads/stores with a scalar base and a 32-bit vector
+// offset.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> global(T* p) { return (gptr<T>)p; }
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ uint64_t lanes_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }
@@ -184,19 +195,33 @@ void k_tile_label(BatchRef ref) {
     }
     const float* src = d.range + (size_t)r0 * W + c0;
     if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(d.range) & 15) == 0) {
-        // tw is then a multiple of 4 as well
+        // tw is then a multiple of 4 as well.  Every load of the thread is
+        // issued before the first is used.
         constexpr int Q = RS / 4;
-        for (int i = threadIdx.x; i < (TH + kPad) * Q; i += kLabelThreads) {
+        constexpr int NQ = (TH + kPad) * Q;
+        constexpr int IT = (NQ + kLabelThreads - 1) / kLabelThreads;
+        const gptr<const float> gsrc = global(src);
+        f32x4 v[IT];
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            const int i = threadIdx.x + u * kLabelThreads;
             const int lr = i / Q, lc = (i % Q) * 4;
-            float4 v = make_float4(nan, nan, nan, nan);
-            if (lr < th && lc < tw) {
-                v = *reinterpret_cast<const float4*>(src + (size_t)lr * W + lc);
-                v.x = measurement_or_nan(v.x);
-                v.y = measurement_or_nan(v.y);
-                v.z = measurement_or_nan(v.z);
-                v.w = measurement_or_nan(v.w);
+            v[u] = f32x4{nan, nan, nan, nan};
+            if (i < NQ && lr < th && lc < tw)
+                v[u] = *reinterpret_cast<gptr<const f32x4>>(gsrc + (unsigned)(lr * W + lc));
+        }
+#pragma unroll
+        for (int u = 0; u < IT; ++u) {
+            const int i = threadIdx.x + u * kLabelThreads;
+            const int lr = i / Q, lc = (i % Q) * 4;
+            if (i < NQ) {
+                f32x4 w = v[u];
+                w.x = measurement_or_nan(w.x);
+                w.y = measurement_or_nan(w.y);
+                w.z = measurement_or_nan(w.z);
+                w.w = measurement_or_nan(w.w);
+                *reinterpret_cast<f32x4*>(&rs[lr * RS + lc]) = w;
             }
-            *reinterpret_cast<float4*>(&rs[lr * RS + lc]) = v;
         }
     } else {
         for (int i = threadIdx.x; i < (TH + kPad) * RS; i += kLabelThreads) {
@@ -308,8 +333,11 @@ void k_tile_label(BatchRef ref) {
     // parent[root] = root for every tile root.
     const int base = r0 * W + c0;
     const bool chunk_in = ch * 64 < tw;                  // chunk lies in the image
-    ulonglong2* mrow = d.masks + (size_t)r0 * d.chunks_per_row + c0 / 64 + ch;
-    int* lrow = d.labels + (size_t)r0 * W + c0 + ch * 64;
+    const gptr<u64x2> masks = global(reinterpret_cast<u64x2*>(d.masks));
+    const gptr<int> labels = global(d.labels);
+    const gptr<int> parent = global(d.parent);
+    const unsigned mbase = r0 * d.chunks_per_row + c0 / 64 + ch;
+    const unsigned lbase = base + ch * 64;
     const uint64_t below = le >> 1;                       // lanes < lane
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
@@ -318,42 +346,40 @@ void k_tile_label(BatchRef ref) {
         const bool head = (heads >> j) & 1;
         const uint64_t vmask = ballot((valids >> j) & 1);
         const uint64_t starts = ballot(head);
-        if (lane == 0) mrow[(size_t)r * d.chunks_per_row] = make_ulonglong2(starts, vmask);
+        if (lane == 0) masks[mbase + r * d.chunks_per_row] = u64x2{starts, vmask};
         if (head) {
             const int i = r * TW + c;
             const int root = lds_find(par, i);
-            const int groot = base + (root / TW) * W + (root % TW);
-            lrow[(size_t)r * W + __popcll(starts & below)] = groot;
-            if (root == i) d.parent[groot] = groot;
+            const unsigned groot = base + (root / TW) * W + (root % TW);
+            labels[lbase + r * W + __popcll(starts & below)] = groot;
+            if (root == i) parent[groot] = groot;
         }
     }
 
     // Output 2: range and global root of the border columns (and rows),
-    // one thread per border pixel, contiguous along the border.
+    // one thread per border slot, contiguous along the border.  Slots are
+    // laid out for a full tile (TH rows, TW columns), so the item index is the
+    // slot offset within the tile's block and every divisor is a constant.
     const bool many_rows = d.tiles_y > 1;
-    const int ncol_items = 2 * N * th;
-    const int nrow_items = many_rows ? 2 * N * tw : 0;
-    for (int it = threadIdx.x; it < ncol_items + nrow_items; it += kLabelThreads) {
+    constexpr int kColItems = 2 * N * TH, kRowItems = 2 * N * TW;
+    const gptr<float> bcol_v = global(d.bcol_v) + (unsigned)(tile * kColItems);
+    const gptr<int> bcol_r = global(d.bcol_r) + (unsigned)(tile * kColItems);
+    const gptr<float> brow_v = global(d.brow_v) + (unsigned)(tile * kRowItems);
+    const gptr<int> brow_r = global(d.brow_r) + (unsigned)(tile * kRowItems);
+    for (int it = threadIdx.x; it < kColItems + (many_rows ? kRowItems : 0); it += kLabelThreads) {
         int rr, cc;
-        size_t at;
-        bool side_col;
-        if (it < ncol_items) {
-            const int side = it / (N * th), rem = it % (N * th);
-            const int slot = rem / th;
-            rr = rem % th;
+        const bool side_col = it < kColItems;
+        if (side_col) {
+            const int side = it / (N * TH), slot = (it / TH) % N;
+            rr = it % TH;
             cc = side == 0 ? slot : tw - N + slot;
-            at = (((size_t)tile * 2 + side) * N + slot) * TH + rr;
-            side_col = true;
         } else {
-            const int k = it - ncol_items;
-            const int side = k / (N * tw), rem = k % (N * tw);
-            const int slot = rem / tw;
-            cc = rem % tw;
+            const int k = it - kColItems;
+            const int side = k / (N * TW), slot = (k / TW) % N;
+            cc = k % TW;
             rr = side == 0 ? slot : th - N + slot;
-            at = (((size_t)tile * 2 + side) * N + slot) * TW + cc;
-            side_col = false;
         }
-        if (cc < 0 || cc >= tw || rr < 0 || rr >= th) continue;   // tile narrower than N
+        if (cc < 0 || cc >= tw || rr < 0 || rr >= th) continue;   // outside the image part
         const float v = rs[rr * RS + cc];
         const int p = par[rr * TW + cc];
         int groot = -1;
@@ -362,11 +388,11 @@ void k_tile_label(BatchRef ref) {
             groot = base + (root / TW) * W + (root % TW);
         }
         if (side_col) {
-            d.bcol_v[at] = v;
-            d.bcol_r[at] = groot;
+            bcol_v[it] = v;
+            bcol_r[it] = groot;
         } else {
-            d.brow_v[at] = v;
-            d.brow_r[at] = groot;
+            brow_v[it - kColItems] = v;
+            brow_r[it - kColItems] = groot;
         }
     }
 }
