@@ -314,16 +314,30 @@ void k_tile_label(BatchRef ref) {
     }
     __syncthreads();
 
+    // Join.  Each lane walks all of its own (row, edge) bits in row order,
+    // packed 2N bits per row into 64-bit words, so a wavefront takes as many
+    // rounds as its busiest lane has edges (not the sum over rows of each
+    // row's busiest lane).
+    {
+        constexpr int P = 2 * N;                          // todo bits per row
+        constexpr int RPW = 64 / P;                       // rows per word
+        constexpr int NW = (kRowsPerWave + RPW - 1) / RPW;
+        uint64_t pend[NW];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) {
-        const int i = (R0 + j) * TW + c;
-        uint32_t t = todo[j];
-        if (ballot(t != 0) == 0) continue;              // nothing to join in this row
-        while (t) {
-            const int b = __builtin_ctz(t);
-            t &= t - 1;
-            const int other = b == 0 ? i + 1 : (b <= N ? i + b * TW : i + (b - N + 1));
-            lds_unite(par, i, other);
+        for (int w = 0; w < NW; ++w) pend[w] = 0;
+#pragma unroll
+        for (int j = 0; j < kRowsPerWave; ++j) pend[j / RPW] |= (uint64_t)todo[j] << ((j % RPW) * P);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            uint64_t m = pend[w];
+            while (m) {
+                const int bit = __builtin_ctzll(m);
+                m &= m - 1;
+                const int j = w * RPW + bit / P, b = bit % P;
+                const int i = (R0 + j) * TW + c;
+                const int other = b == 0 ? i + 1 : (b <= N ? i + b * TW : i + (b - N + 1));
+                lds_unite(par, i, other);
+            }
         }
     }
     __syncthreads();
@@ -618,6 +632,13 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
 
 // ---- pass 3: run lists -> labels ---------------------------------------------
 
+// The 64-bit value lane j holds, as a wave-uniform value.
+__device__ __forceinline__ uint64_t lane_word(uint64_t v, int j) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ int root_of(const int* par, int x) {
     int p = par[x];
     while (p != x) {
@@ -627,10 +648,19 @@ __device__ __forceinline__ int root_of(const int* par, int x) {
     return x;
 }
 
+// One workgroup per tile, 16 rows of one 64-column chunk per wavefront: each
+// wavefront issues the masks of all its rows (one per lane) and the heads of
+// their run lists at once, so two dependent memory round trips cover 1024
+// pixels.
+constexpr int kRelabelRows = 16;
+constexpr int kRelabelThreads = kTilePx / kRelabelRows;
+
 template <int TW>
-__global__ __launch_bounds__(kLabelThreads) void k_relabel(BatchRef ref) {
+__global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
     constexpr int CH = TW / 64;
+    static_assert(CH * TH == (kRelabelThreads / 64) * kRelabelRows, "one strip per wavefront");
+    constexpr int kListHead = 16;                 // run-list entries loaded up front
     ScanDesc d;
     int tile;
     locate(ref, blockIdx.x, d, tile);
@@ -639,40 +669,45 @@ __global__ __launch_bounds__(kLabelThreads) void k_relabel(BatchRef ref) {
     const int tw = min(TW, d.W - c0), th = min(TH, d.H - r0);
     const int W = d.W;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ch = wave % CH, R0 = (wave / CH) * kRowsPerWave;
+    const int ch = wave % CH, R0 = (wave / CH) * kRelabelRows;
     const int c = ch * 64 + lane;
     if (ch * 64 >= tw || R0 >= th) return;
-    const int rows = min(kRowsPerWave, th - R0);
+    const int rows = min(kRelabelRows, th - R0);
     const uint64_t le = lanes_le(lane);
-    const ulonglong2* mrow = d.masks + (size_t)(r0 + R0) * d.chunks_per_row + c0 / 64 + ch;
-    int* seg0 = d.labels + (size_t)(r0 + R0) * W + c0 + ch * 64;
     const bool col_in = c < tw;
-    // all loads of the strip first: masks and run lists of every row ...
-    ulonglong2 m[kRowsPerWave];
-    int listed[kRowsPerWave];
+    const gptr<const u64x2> masks = global(reinterpret_cast<const u64x2*>(d.masks));
+    const gptr<int> labels = global(d.labels);
+    const gptr<const int> parent = global(static_cast<const int*>(d.parent));
+    const unsigned mbase = (r0 + R0) * d.chunks_per_row + c0 / 64 + ch;
+    const unsigned lbase = (r0 + R0) * W + c0 + ch * 64;
+    // all loads of the strip first: lane j holds row j's masks; every row's
+    // first kListHead run roots (enough for most chunks) ...
+    const u64x2 mine = lane < rows ? masks[mbase + lane * d.chunks_per_row] : u64x2{0, 0};
+    int listed[kRelabelRows];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) {
-        const bool row_in = j < rows;
-        m[j] = row_in ? mrow[(size_t)j * d.chunks_per_row] : make_ulonglong2(0, 0);
-        listed[j] = (row_in && col_in) ? seg0[(size_t)j * W + lane] : -1;
-    }
-    // ... then every pixel's run root and its final root ...
-    int out[kRowsPerWave];
+    for (int j = 0; j < kRelabelRows; ++j)
+        listed[j] = (j < rows && col_in && lane < kListHead) ? labels[lbase + j * W + lane] : -1;
+    // ... then, row by row: the rest of the list for the rare chunk with more
+    // runs, every pixel's run root and its final root
+    int out[kRelabelRows];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) {
-        const int run = __popcll(m[j].x & le) - 1;
+    for (int j = 0; j < kRelabelRows; ++j) {
+        const uint64_t starts = lane_word(mine.x, j), valid = lane_word(mine.y, j);
+        const int n = __popcll(starts);
+        if (n > kListHead && lane >= kListHead && lane < n) listed[j] = labels[lbase + j * W + lane];
+        const int run = __popcll(starts & le) - 1;
         const int groot = __shfl(listed[j], run < 0 ? 0 : run);
-        out[j] = lane_bit(m[j].y) ? d.parent[groot] : -1;
+        out[j] = lane_bit(valid) ? parent[groot] : -1;
     }
     if (*d.flags) {                                  // some roots were joined uncompressed
 #pragma unroll
-        for (int j = 0; j < kRowsPerWave; ++j)
-            if (lane_bit(m[j].y)) out[j] = root_of(d.parent, out[j]);
+        for (int j = 0; j < kRelabelRows; ++j)
+            if (out[j] >= 0) out[j] = root_of(d.parent, out[j]);
     }
     // ... then the labels (the run lists are overwritten only now)
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j)
-        if (j < rows && col_in) seg0[(size_t)j * W + lane] = out[j];
+    for (int j = 0; j < kRelabelRows; ++j)
+        if (j < rows && col_in) labels[lbase + j * W + lane] = out[j];
 }
 
 template <int TW, int N>
@@ -683,7 +718,7 @@ hipError_t launch_twn(const BatchRef& ref, int n_tiles, int n_scans, hipStream_t
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_scan_merge<TW, N>), dim3(n_scans), dim3(kMergeThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_relabel<TW>, dim3(n_tiles), dim3(kLabelThreads), 0, stream, ref);
+    hipLaunchKernelGGL(k_relabel<TW>, dim3(n_tiles), dim3(kRelabelThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
     return hipGetLastError();
 }
