@@ -138,17 +138,26 @@ __device__ void lds_unite(int* par, int a, int b) {
 
 // ---- pass 1: tile-local labelling ------------------------------------------
 //
-// LDS holds the tile's ranges with kPad extra NaN columns on the right and
-// kPad extra NaN rows below, so every neighbour read is in bounds and an edge
-// that leaves the tile simply tests false (those edges belong to pass 2).
-// Each wavefront owns one 64-column strip of 8 consecutive rows and walks it
-// bottom-up, keeping the values, squares and direct-edge ballots of the N
-// rows below in registers.
+// LDS holds the tile's ranges with N extra NaN rows above and kPad extra NaN
+// columns on the right, so every neighbour read is in bounds and an edge that
+// leaves the tile simply tests false (those edges belong to pass 2).  Each
+// wavefront owns one 64-column strip of 8 consecutive rows and walks it top
+// down, keeping the values, squares and direct-edge ballots of the N rows
+// above in registers.
+//
+// Most direct vertical edges inside a strip need no union-find work: every
+// lane carries the strip-level root of the pixel above it, and a run whose
+// head has a direct vertical edge takes the root above the head as its parent
+// (one lane shuffle).  Only the edges that may join a different tree are left
+// for the join step: the strip's first row, vertical edges of other pixels
+// whose root above differs, skip edges and run joins across strip borders.
 
 constexpr int kPad = 8;            // >= kMaxSkip
 constexpr int kRowsPerWave = 8;    // kTilePx / 64 / kLabelWaves
+constexpr int kNoRoot = 0xffff;    // "no strip root above" (tile indices are < 8192)
 
 // Eq. (4) with both squares already formed: (sq1 + sq2) - ((2 cos a) * (d1 * d2)).
+// Symmetric in its two ends (IEEE addition and multiplication commute).
 __device__ __forceinline__ bool connected_sq(float d1, float sq1, float d2, float sq2,
                                              float two_cos, float t2) {
     float sum = sq1 + sq2;
@@ -168,11 +177,13 @@ void k_tile_label(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
     constexpr int CH = TW / 64;               // 64-column strips per tile row
     constexpr int RS = TW + kPad;             // LDS row stride of the ranges
+    constexpr int LR = TH + N;                // LDS rows: N NaN rows, then the tile
     static_assert(TH * CH == kLabelWaves * kRowsPerWave, "one 8-row strip per wavefront");
-    __shared__ float rs[(TH + kPad) * RS];
+    static_assert(kTilePx <= kNoRoot, "tile indices fit 16 bits");
+    __shared__ float rs[LR * RS];
     __shared__ int par[kTilePx];
     __shared__ float c2h[N][TW];
-    __shared__ float c2v[N][TH + kPad];
+    __shared__ float c2v[N][LR];              // [k-1][x + N]: rows x and x + k
 
     ScanDesc d;
     int tile;
@@ -189,44 +200,45 @@ void k_tile_label(BatchRef ref) {
         const int k = i / TW, c = i % TW;
         c2h[k][c] = (c < tw) ? 2.0f * d.cos_h[(size_t)k * W + c0 + c] : 0.0f;
     }
-    for (int i = threadIdx.x; i < N * (TH + kPad); i += kLabelThreads) {
-        const int k = i / (TH + kPad), r = i % (TH + kPad);
-        c2v[k][r] = (r < th && r0 + r + k + 1 < H) ? 2.0f * d.cos_v[(size_t)k * H + r0 + r] : 0.0f;
+    for (int i = threadIdx.x; i < N * LR; i += kLabelThreads) {
+        const int k = i / LR, x = i % LR - N;
+        c2v[k][x + N] = (x >= 0 && x < th && r0 + x + k + 1 < H)
+                            ? 2.0f * d.cos_v[(size_t)k * H + r0 + x] : 0.0f;
     }
+    // tile row x lives at LDS row x + N
     const float* src = d.range + (size_t)r0 * W + c0;
     if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(d.range) & 15) == 0) {
         // tw is then a multiple of 4 as well.  Every load of the thread is
         // issued before the first is used.
         constexpr int Q = RS / 4;
-        constexpr int NQ = (TH + kPad) * Q;
+        constexpr int NQ = LR * Q;
         constexpr int IT = (NQ + kLabelThreads - 1) / kLabelThreads;
         const gptr<const float> gsrc = global(src);
         f32x4 v[IT];
 #pragma unroll
         for (int u = 0; u < IT; ++u) {
             const int i = threadIdx.x + u * kLabelThreads;
-            const int lr = i / Q, lc = (i % Q) * 4;
+            const int x = i / Q - N, lc = (i % Q) * 4;
             v[u] = f32x4{nan, nan, nan, nan};
-            if (i < NQ && lr < th && lc < tw)
-                v[u] = *reinterpret_cast<gptr<const f32x4>>(gsrc + (unsigned)(lr * W + lc));
+            if (i < NQ && x >= 0 && x < th && lc < tw)
+                v[u] = *reinterpret_cast<gptr<const f32x4>>(gsrc + (unsigned)(x * W + lc));
         }
 #pragma unroll
         for (int u = 0; u < IT; ++u) {
             const int i = threadIdx.x + u * kLabelThreads;
-            const int lr = i / Q, lc = (i % Q) * 4;
             if (i < NQ) {
                 f32x4 w = v[u];
                 w.x = measurement_or_nan(w.x);
                 w.y = measurement_or_nan(w.y);
                 w.z = measurement_or_nan(w.z);
                 w.w = measurement_or_nan(w.w);
-                *reinterpret_cast<f32x4*>(&rs[lr * RS + lc]) = w;
+                *reinterpret_cast<f32x4*>(&rs[(i / Q) * RS + (i % Q) * 4]) = w;
             }
         }
     } else {
-        for (int i = threadIdx.x; i < (TH + kPad) * RS; i += kLabelThreads) {
-            const int lr = i / RS, lc = i % RS;
-            rs[i] = (lr < th && lc < tw) ? measurement_or_nan(src[(size_t)lr * W + lc]) : nan;
+        for (int i = threadIdx.x; i < LR * RS; i += kLabelThreads) {
+            const int x = i / RS - N, lc = i % RS;
+            rs[i] = (x >= 0 && x < th && lc < tw) ? measurement_or_nan(src[(size_t)x * W + lc]) : nan;
         }
     }
     __syncthreads();
@@ -234,44 +246,48 @@ void k_tile_label(BatchRef ref) {
     const int ch = wave % CH, R0 = (wave / CH) * kRowsPerWave;
     const int c = ch * 64 + lane;
     const uint64_t le = lanes_le(lane);
+    const float* at = rs + N * RS + c;                    // at[x * RS + k]: tile row x, column c + k
     float c2hk[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) c2hk[k] = c2h[k][c];
 
-    // Window of the N rows below the current one: value, square, direct
-    // horizontal ballot (h1) and direct vertical ballot (v1) of each.
+    // Window of the N rows above the current one: value, square, direct
+    // horizontal ballot (h1) and direct vertical ballot to the row above it
+    // (v1; needed for the N-1 nearest rows only).
     float wv[N], ws[N];
     uint64_t wh1[N], wv1[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        const int q = R0 + kRowsPerWave + j;            // < TH + kPad
-        wv[j] = rs[q * RS + c];
+        const int x = R0 - 1 - j;                         // >= -N
+        wv[j] = at[x * RS];
         ws[j] = wv[j] * wv[j];
-        const float right = rs[q * RS + c + 1];
-        const float below = rs[(q + 1 < TH + kPad ? q + 1 : q) * RS + c];
+        const float right = at[x * RS + 1];
         wh1[j] = ballot(connected_sq(wv[j], ws[j], right, right * right, c2hk[0], t2));
-        wv1[j] = (q + 1 < TH + kPad)
-                     ? ballot(connected_sq(wv[j], ws[j], below, below * below, c2v[0][q], t2))
-                     : 0;
+        wv1[j] = 0;
+        if (j + 1 < N) {                                  // row x - 1 >= -N
+            const float up = at[(x - 1) * RS];
+            wv1[j] = ballot(connected_sq(up, up * up, wv[j], ws[j], c2v[0][x - 1 + N], t2));
+        }
     }
 
-    // Edge ballots row by row (bottom-up).  todo bit 0: the next pixel
-    // across a strip border; bit k (1..N): k rows down; bit N+k-1 (k >= 2):
-    // k columns right.  A bit is set only when the edge is not implied.
+    // Edge ballots row by row (top-down).  todo bit 0: the next pixel across
+    // a strip border; bit k (1..N): k rows up; bit N+k-1 (k >= 2): k columns
+    // right.  A bit is set only when the edge may join two different trees.
     uint32_t todo[kRowsPerWave];
     uint32_t heads = 0, valids = 0;                      // bit j: row R0 + j
+    int above = kNoRoot;                                 // strip root of the pixel above
 #pragma unroll
-    for (int j = kRowsPerWave - 1; j >= 0; --j) {
+    for (int j = 0; j < kRowsPerWave; ++j) {
         const int r = R0 + j;
-        const float a = rs[r * RS + c];
+        const float a = at[r * RS];
         const float sa = a * a;
-        uint64_t h1 = 0, v1 = 0, chain = 0, run = 0;
+        uint64_t h1 = 0, v1 = 0, link = 0, chain = 0, run = 0;
         uint32_t t = 0;
 #pragma unroll
         for (int k = 1; k <= N; ++k) {
-            const float b = rs[r * RS + c + k];
+            const float b = at[r * RS + k];
             const uint64_t hk = ballot(connected_sq(a, sa, b, b * b, c2hk[k - 1], t2));
-            const uint64_t vk = ballot(connected_sq(a, sa, wv[k - 1], ws[k - 1], c2v[k - 1][r], t2));
+            const uint64_t vk = ballot(connected_sq(wv[k - 1], ws[k - 1], a, sa, c2v[k - 1][r - k + N], t2));
             if (k == 1) {
                 h1 = hk;
                 v1 = vk;
@@ -285,18 +301,29 @@ void k_tile_label(BatchRef ref) {
                 if (lane_bit(hneed)) t |= 1u << (N + k - 1);
             }
             uint64_t vneed = vk & ~((vk & h1 & wh1[k - 1]) << 1);
-            if (k >= 2) vneed &= ~chain;
-            if (lane_bit(vneed)) t |= 1u << k;
+            if (k >= 2) {
+                vneed &= ~chain;
+                if (lane_bit(vneed)) t |= 1u << k;
+            } else {
+                link = vneed;                             // pruned direct vertical edges
+            }
         }
         const bool valid = a == a;
         const int head = 63 - __clzll(~(h1 << 1) & le);   // first pixel of the run
-        par[r * TW + c] = valid ? r * TW + ch * 64 + head : -1;
+        // a run whose head has a (pruned) direct vertical edge takes the strip
+        // root above the head; any other run is a new strip root
+        const bool up = lane_bit(link);
+        const int got = __shfl(up ? above : kNoRoot, head);
+        const int root = got != kNoRoot ? got : r * TW + ch * 64 + head;
+        par[r * TW + c] = valid ? root : -1;
+        if (up && above != root) t |= 2u;                // may join another tree above
         if (valid && head == lane) heads |= 1u << j;
         if (valid) valids |= 1u << j;
+        above = valid ? root : kNoRoot;
         // materialise this row's per-lane results here: otherwise the compiler
         // sinks them to their uses after the barrier and keeps the 64-bit
         // masks alive (spilled) instead
-        asm volatile("" : "+v"(t), "+v"(heads), "+v"(valids));
+        asm volatile("" : "+v"(t), "+v"(heads), "+v"(valids), "+v"(above));
         todo[j] = t;
 #pragma unroll
         for (int k = N - 1; k >= 1; --k) {
@@ -335,7 +362,7 @@ void k_tile_label(BatchRef ref) {
                 m &= m - 1;
                 const int j = w * RPW + bit / P, b = bit % P;
                 const int i = (R0 + j) * TW + c;
-                const int other = b == 0 ? i + 1 : (b <= N ? i + b * TW : i + (b - N + 1));
+                const int other = b == 0 ? i + 1 : (b <= N ? i - b * TW : i + (b - N + 1));
                 lds_unite(par, i, other);
             }
         }
@@ -394,7 +421,7 @@ void k_tile_label(BatchRef ref) {
             rr = side == 0 ? slot : th - N + slot;
         }
         if (cc < 0 || cc >= tw || rr < 0 || rr >= th) continue;   // outside the image part
-        const float v = rs[rr * RS + cc];
+        const float v = rs[(rr + N) * RS + cc];
         const int p = par[rr * TW + cc];
         int groot = -1;
         if (p >= 0) {
