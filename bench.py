@@ -26,6 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE_RECORD = os.path.join(ROOT, "profiles", "flic_passes_large_batch_64x128x2048.txt")
+# vector-instruction issue peak: 256 CUs x one wave64 VALU instruction per CU
+# per cycle (4 SIMD16 units, 4 cycles each) x 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 2.4e9
 THRESHOLDS = (0.3, 0.5, 1.0)
 N_SCANS, H, W, SKIP = 64, 128, 2048, 3
 
@@ -78,6 +82,16 @@ def uneven_batch(ctx, flic, synth, torch, dev, stream, n=256, reps=10):
             "per_scan_gpix_s": round(px / (single_ms * 1e-3) / 1e9, 3),
             "plan_scans_s": round(n / (plan_ms * 1e-3), 1),
             "per_scan_scans_s": round(n / (single_ms * 1e-3), 1)}
+
+
+def dominant_traffic(name):
+    """HBM bytes of one launch of the named pass from the committed rocprofv3
+    record, or None when there is none or the kernel source changed since."""
+    from paper_2003_00575_amd import prof_summary
+    rec = prof_summary.load_record(PROFILE_RECORD)
+    if not rec or rec.get("kernel_source_sha256") != prof_summary.kernel_source_sha256():
+        return None
+    return rec.get("kernels", {}).get(name)
 
 
 def serving_excerpt(seconds, speedups=(4.0, 16.0), sensors=32):
@@ -281,6 +295,8 @@ def main() -> int:
     serving = None if args.no_serve else serving_excerpt(args.serve_seconds)
 
     # ---- CPU oracle on a bounded sample -------------------------------------
+    traffic = dominant_traffic(names[dom])
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -315,9 +331,19 @@ def main() -> int:
                    "global_batch": N_SCANS * len(THRESHOLDS), "pixels_per_step": px_per_step,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic.get("traffic_bytes") if traffic else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_record": None if traffic is None else {
+                         "file": os.path.relpath(PROFILE_RECORD, ROOT),
+                         "fetch_bytes": traffic.get("fetch_bytes"), "write_bytes": traffic.get("write_bytes"),
+                         "rocprof_mean_us": traffic.get("mean_us")},
                      "kernel": names[dom], "kernel_ms_per_launch": round(avg[dom], 5),
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "valu_issue": None if not traffic or "sq" not in traffic else {
+                         "valu_instructions_per_launch": traffic["sq"]["SQ_INSTS_VALU"],
+                         "peak_per_s": VALU_ISSUE_PEAK,
+                         "frac": round(traffic["sq"]["SQ_INSTS_VALU"] / (avg[dom] * 1e-3) / VALU_ISSUE_PEAK, 4)}},
         "passes_ms_per_launch": {n: round(a, 5) for n, a in zip(names, avg)},
         "path_effective_GBs": round(value * 8.0, 1),
         "per_scan_launches": {"gpix_s": round(single_gpix, 3),
