@@ -79,6 +79,12 @@ __device__ __forceinline__ gptr<T> global(T* p) { return (gptr<T>)p; }
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
+// The wavefront's index in its workgroup, as a wave-uniform (scalar) value,
+// so that everything derived from it is scalar arithmetic.
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
 __device__ __forceinline__ uint64_t lanes_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }
@@ -193,7 +199,7 @@ void k_tile_label(BatchRef ref) {
     const int tw = min(TW, d.W - c0), th = min(TH, d.H - r0);
     const int W = d.W, H = d.H;
     const float t2 = d.t2;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const float nan = __builtin_nanf("");
 
     for (int i = threadIdx.x; i < N * TW; i += kLabelThreads) {
@@ -374,28 +380,50 @@ void k_tile_label(BatchRef ref) {
     // parent[root] = root for every tile root.
     const int base = r0 * W + c0;
     const bool chunk_in = ch * 64 < tw;                  // chunk lies in the image
-    const gptr<u64x2> masks = global(reinterpret_cast<u64x2*>(d.masks));
+    const int rows = chunk_in ? max(0, min(kRowsPerWave, th - R0)) : 0;
+    const gptr<unsigned> mask_words = global(reinterpret_cast<unsigned*>(d.masks));
     const gptr<int> labels = global(d.labels);
     const gptr<int> parent = global(d.parent);
-    const unsigned mbase = r0 * d.chunks_per_row + c0 / 64 + ch;
-    const unsigned lbase = base + ch * 64;
+    const unsigned mbase = (r0 + R0) * d.chunks_per_row + c0 / 64 + ch;
+    const unsigned lbase = base + R0 * W + ch * 64;
     const uint64_t below = le >> 1;                       // lanes < lane
+    // roots of the strip's run heads: the 8 rows' walks interleaved
+    int node[kRowsPerWave];
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) node[j] = ((heads >> j) & 1) ? (R0 + j) * TW + c : -1;
+    for (;;) {
+        bool moved = false;
+#pragma unroll
+        for (int j = 0; j < kRowsPerWave; ++j) {
+            const int p = lds_load(&par[node[j] < 0 ? 0 : node[j]]);
+            if (node[j] >= 0 && p != node[j]) {
+                node[j] = p;
+                moved = true;
+            }
+        }
+        if (ballot(moved) == 0) break;
+    }
+    // the masks of all rows in one store: lane 4j + q holds 32-bit word q of
+    // row j's (run starts, measurements) pair
+    unsigned words = 0;
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
-        const int r = R0 + j;
-        if (r >= th || !chunk_in) break;
         const bool head = (heads >> j) & 1;
-        const uint64_t vmask = ballot((valids >> j) & 1);
         const uint64_t starts = ballot(head);
-        if (lane == 0) masks[mbase + r * d.chunks_per_row] = u64x2{starts, vmask};
-        if (head) {
-            const int i = r * TW + c;
-            const int root = lds_find(par, i);
+        const uint64_t vmask = ballot((valids >> j) & 1);
+        words = lane_bit(1ull << (4 * j + 0)) ? (unsigned)starts : words;
+        words = lane_bit(1ull << (4 * j + 1)) ? (unsigned)(starts >> 32) : words;
+        words = lane_bit(1ull << (4 * j + 2)) ? (unsigned)vmask : words;
+        words = lane_bit(1ull << (4 * j + 3)) ? (unsigned)(vmask >> 32) : words;
+        if (head && j < rows) {
+            const unsigned i = (R0 + j) * TW + c, root = node[j];
             const unsigned groot = base + (root / TW) * W + (root % TW);
-            labels[lbase + r * W + __popcll(starts & below)] = groot;
+            labels[lbase + j * W + __popcll(starts & below)] = groot;
             if (root == i) parent[groot] = groot;
         }
     }
+    if (lane < 4 * rows)
+        mask_words[4 * (mbase + (lane >> 2) * d.chunks_per_row) + (lane & 3)] = words;
 
     // Output 2: range and global root of the border columns (and rows),
     // one thread per border slot, contiguous along the border.  Slots are
@@ -515,7 +543,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
     const ScanDesc d = ref.descs ? ref.descs[blockIdx.x] : ref.one;
     const int W = d.W, H = d.H;
     const float t2 = d.t2;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     int* par = d.parent;
     for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) set[i] = kEmpty;
     if (threadIdx.x == 0) overflow = 0;
@@ -695,7 +723,7 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     const int c0 = tx * TW, r0 = ty * TH;
     const int tw = min(TW, d.W - c0), th = min(TH, d.H - r0);
     const int W = d.W;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int ch = wave % CH, R0 = (wave / CH) * kRelabelRows;
     const int c = ch * 64 + lane;
     if (ch * 64 >= tw || R0 >= th) return;
