@@ -177,6 +177,27 @@ __device__ __forceinline__ bool lane_bit(uint64_t mask) {
     return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
 
+// Border slot `it` of a tile (laid out for a full TH x TW tile): the first
+// 2*N*TH slots are the first and last N columns (slot-major, row-minor), the
+// next 2*N*TW the first and last N rows.  Gives the pixel's tile row and
+// column; false when the slot lies outside the image part of the tile.
+template <int TW, int N>
+__device__ __forceinline__ bool border_slot(int it, int tw, int th, int& rr, int& cc) {
+    constexpr int TH = kTilePx / TW;
+    constexpr int kColItems = 2 * N * TH;
+    if (it < kColItems) {
+        const int side = it / (N * TH), slot = (it / TH) % N;
+        rr = it % TH;
+        cc = side == 0 ? slot : tw - N + slot;
+    } else {
+        const int k = it - kColItems;
+        const int side = k / (N * TW), slot = (k / TW) % N;
+        cc = k % TW;
+        rr = side == 0 ? slot : th - N + slot;
+    }
+    return cc >= 0 && cc < tw && rr >= 0 && rr < th;
+}
+
 template <int TW, int N>
 __global__ __launch_bounds__(kLabelThreads) __attribute__((amdgpu_waves_per_eu(N <= 3 ? 8 : 4)))
 void k_tile_label(BatchRef ref) {
@@ -213,13 +234,13 @@ void k_tile_label(BatchRef ref) {
     }
     // tile row x lives at LDS row x + N
     const float* src = d.range + (size_t)r0 * W + c0;
+    const gptr<const float> gsrc = global(src);
     if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(d.range) & 15) == 0) {
         // tw is then a multiple of 4 as well.  Every load of the thread is
         // issued before the first is used.
         constexpr int Q = RS / 4;
         constexpr int NQ = LR * Q;
         constexpr int IT = (NQ + kLabelThreads - 1) / kLabelThreads;
-        const gptr<const float> gsrc = global(src);
         f32x4 v[IT];
 #pragma unroll
         for (int u = 0; u < IT; ++u) {
@@ -248,6 +269,20 @@ void k_tile_label(BatchRef ref) {
         }
     }
     __syncthreads();
+
+    // Border slots (one thread each): their ranges are taken now, while the
+    // range buffer still holds them.
+    const bool many_rows = d.tiles_y > 1;
+    constexpr int kColItems = 2 * N * TH, kRowItems = 2 * N * TW;
+    constexpr int kSlotRounds = (kColItems + kRowItems + kLabelThreads - 1) / kLabelThreads;
+    const int n_slots = kColItems + (many_rows ? kRowItems : 0);
+    float slot_v[kSlotRounds];
+#pragma unroll
+    for (int u = 0; u < kSlotRounds; ++u) {
+        const int it = threadIdx.x + u * kLabelThreads;
+        int rr = 0, cc = 0;
+        slot_v[u] = (it < n_slots && border_slot<TW, N>(it, tw, th, rr, cc)) ? rs[(rr + N) * RS + cc] : nan;
+    }
 
     const int ch = wave % CH, R0 = (wave / CH) * kRowsPerWave;
     const int c = ch * 64 + lane;
@@ -280,7 +315,7 @@ void k_tile_label(BatchRef ref) {
     // a strip border; bit k (1..N): k rows up; bit N+k-1 (k >= 2): k columns
     // right.  A bit is set only when the edge may join two different trees.
     uint32_t todo[kRowsPerWave];
-    uint32_t heads = 0, valids = 0;                      // bit j: row R0 + j
+    uint32_t heads = 0, valids = 0, sroots = 0;          // bit j: row R0 + j
     int above = kNoRoot;                                 // strip root of the pixel above
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
@@ -324,12 +359,13 @@ void k_tile_label(BatchRef ref) {
         par[r * TW + c] = valid ? root : -1;
         if (up && above != root) t |= 2u;                // may join another tree above
         if (valid && head == lane) heads |= 1u << j;
+        if (valid && head == lane && got == kNoRoot) sroots |= 1u << j;   // a new strip root
         if (valid) valids |= 1u << j;
         above = valid ? root : kNoRoot;
         // materialise this row's per-lane results here: otherwise the compiler
         // sinks them to their uses after the barrier and keeps the 64-bit
         // masks alive (spilled) instead
-        asm volatile("" : "+v"(t), "+v"(heads), "+v"(valids), "+v"(above));
+        asm volatile("" : "+v"(t), "+v"(heads), "+v"(valids), "+v"(sroots), "+v"(above));
         todo[j] = t;
 #pragma unroll
         for (int k = N - 1; k >= 1; --k) {
@@ -347,30 +383,57 @@ void k_tile_label(BatchRef ref) {
     }
     __syncthreads();
 
-    // Join.  Each lane walks all of its own (row, edge) bits in row order,
-    // packed 2N bits per row into 64-bit words, so a wavefront takes as many
-    // rounds as its busiest lane has edges (not the sum over rows of each
-    // row's busiest lane).
+    // The range buffer is free now: each wavefront uses its 512-entry slice
+    // of it as a queue.  Every pixel's parent is its strip root, and every
+    // tree node above a pixel is a strip root.
+    static_assert(kTilePx <= (1 << 13) && 2 * kMaxSkip <= 32 - 13, "queue entry packing");
+    static_assert(kLabelWaves * kRowsPerWave * 64 <= LR * RS, "queues fit the range buffer");
+    int* queue = reinterpret_cast<int*>(rs) + wave * (kRowsPerWave * 64);
+    const uint64_t below = le >> 1;                       // lanes < lane
+
+    // Join: the strip's pixels with join bits (index | bits << 13), one lane
+    // per pixel (about three per strip).
     {
-        constexpr int P = 2 * N;                          // todo bits per row
-        constexpr int RPW = 64 / P;                       // rows per word
-        constexpr int NW = (kRowsPerWave + RPW - 1) / RPW;
-        uint64_t pend[NW];
+        int count = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) pend[w] = 0;
-#pragma unroll
-        for (int j = 0; j < kRowsPerWave; ++j) pend[j / RPW] |= (uint64_t)todo[j] << ((j % RPW) * P);
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            uint64_t m = pend[w];
-            while (m) {
-                const int bit = __builtin_ctzll(m);
-                m &= m - 1;
-                const int j = w * RPW + bit / P, b = bit % P;
-                const int i = (R0 + j) * TW + c;
+        for (int j = 0; j < kRowsPerWave; ++j) {
+            const uint64_t m = ballot(todo[j] != 0);
+            if (todo[j]) queue[count + __popcll(m & below)] = ((R0 + j) * TW + c) | (int)(todo[j] << 13);
+            count += __popcll(m);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int e = lane; e < count; e += 64) {
+            const int w = queue[e];
+            const int i = w & (kTilePx - 1);
+            uint32_t t = (uint32_t)w >> 13;
+            while (t) {
+                const int b = __builtin_ctz(t);
+                t &= t - 1;
                 const int other = b == 0 ? i + 1 : (b <= N ? i - b * TW : i + (b - N + 1));
                 lds_unite(par, i, other);
             }
+        }
+    }
+    __syncthreads();
+
+    // Compress: every strip root is pointed at its final root.  Joins hook
+    // whole chains of strip roots (a tall component has one per strip);
+    // the concurrent halving finds shorten them like pointer jumping.
+    {
+        int count = 0;
+#pragma unroll
+        for (int j = 0; j < kRowsPerWave; ++j) {
+            const bool sr = (sroots >> j) & 1;
+            const uint64_t m = ballot(sr);
+            if (sr) queue[count + __popcll(m & below)] = (R0 + j) * TW + c;
+            count += __popcll(m);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int e = lane; e < count; e += 64) {
+            const int x = queue[e];
+            const int root = lds_find(par, x);
+            if (root != x)
+                __hip_atomic_fetch_min(&par[x], root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     __syncthreads();
@@ -386,23 +449,14 @@ void k_tile_label(BatchRef ref) {
     const gptr<int> parent = global(d.parent);
     const unsigned mbase = (r0 + R0) * d.chunks_per_row + c0 / 64 + ch;
     const unsigned lbase = base + R0 * W + ch * 64;
-    const uint64_t below = le >> 1;                       // lanes < lane
-    // roots of the strip's run heads: the 8 rows' walks interleaved
+    // final roots of the strip's run heads: two reads (head -> strip root ->
+    // final root), the 8 rows' reads issued together
     int node[kRowsPerWave];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) node[j] = ((heads >> j) & 1) ? (R0 + j) * TW + c : -1;
-    for (;;) {
-        bool moved = false;
+    for (int j = 0; j < kRowsPerWave; ++j)
+        node[j] = ((heads >> j) & 1) ? lds_load(&par[(R0 + j) * TW + c]) : 0;
 #pragma unroll
-        for (int j = 0; j < kRowsPerWave; ++j) {
-            const int p = lds_load(&par[node[j] < 0 ? 0 : node[j]]);
-            if (node[j] >= 0 && p != node[j]) {
-                node[j] = p;
-                moved = true;
-            }
-        }
-        if (ballot(moved) == 0) break;
-    }
+    for (int j = 0; j < kRowsPerWave; ++j) node[j] = lds_load(&par[node[j]]);
     // the masks of all rows in one store: lane 4j + q holds 32-bit word q of
     // row j's (run starts, measurements) pair
     unsigned words = 0;
@@ -425,42 +479,29 @@ void k_tile_label(BatchRef ref) {
     if (lane < 4 * rows)
         mask_words[4 * (mbase + (lane >> 2) * d.chunks_per_row) + (lane & 3)] = words;
 
-    // Output 2: range and global root of the border columns (and rows),
-    // one thread per border slot, contiguous along the border.  Slots are
-    // laid out for a full tile (TH rows, TW columns), so the item index is the
-    // slot offset within the tile's block and every divisor is a constant.
-    const bool many_rows = d.tiles_y > 1;
-    constexpr int kColItems = 2 * N * TH, kRowItems = 2 * N * TW;
+    // Output 2: range and global root of the border columns (and rows), one
+    // thread per border slot, contiguous along the border.  The slot index is
+    // the offset within the tile's block.
     const gptr<float> bcol_v = global(d.bcol_v) + (unsigned)(tile * kColItems);
     const gptr<int> bcol_r = global(d.bcol_r) + (unsigned)(tile * kColItems);
     const gptr<float> brow_v = global(d.brow_v) + (unsigned)(tile * kRowItems);
     const gptr<int> brow_r = global(d.brow_r) + (unsigned)(tile * kRowItems);
-    for (int it = threadIdx.x; it < kColItems + (many_rows ? kRowItems : 0); it += kLabelThreads) {
+#pragma unroll
+    for (int u = 0; u < kSlotRounds; ++u) {
+        const int it = threadIdx.x + u * kLabelThreads;
         int rr, cc;
-        const bool side_col = it < kColItems;
-        if (side_col) {
-            const int side = it / (N * TH), slot = (it / TH) % N;
-            rr = it % TH;
-            cc = side == 0 ? slot : tw - N + slot;
-        } else {
-            const int k = it - kColItems;
-            const int side = k / (N * TW), slot = (k / TW) % N;
-            cc = k % TW;
-            rr = side == 0 ? slot : th - N + slot;
-        }
-        if (cc < 0 || cc >= tw || rr < 0 || rr >= th) continue;   // outside the image part
-        const float v = rs[(rr + N) * RS + cc];
+        if (it >= n_slots || !border_slot<TW, N>(it, tw, th, rr, cc)) continue;
         const int p = par[rr * TW + cc];
         int groot = -1;
         if (p >= 0) {
-            const int root = lds_find(par, p);
+            const unsigned root = par[p];                // strip root -> final root
             groot = base + (root / TW) * W + (root % TW);
         }
-        if (side_col) {
-            bcol_v[it] = v;
+        if (it < kColItems) {
+            bcol_v[it] = slot_v[u];
             bcol_r[it] = groot;
         } else {
-            brow_v[it - kColItems] = v;
+            brow_v[it - kColItems] = slot_v[u];
             brow_r[it - kColItems] = groot;
         }
     }
