@@ -186,12 +186,12 @@ ScanDesc make_desc(const flic_scan& s, int tile_w, int32_t tile_begin, char* scr
     d.tile_begin = tile_begin;
     const flic::ScratchLayout S = flic::scratch_layout(s.H, s.W, s.skip_depth, tile_w);
     d.masks = reinterpret_cast<ulonglong2*>(scratch + S.masks);
+    d.runs = reinterpret_cast<uint16_t*>(scratch + S.runs);
     d.parent = reinterpret_cast<int32_t*>(scratch + S.parent);
     d.bcol_v = reinterpret_cast<float*>(scratch + S.bcol_v);
     d.bcol_r = reinterpret_cast<int32_t*>(scratch + S.bcol_r);
     d.brow_v = reinterpret_cast<float*>(scratch + S.brow_v);
     d.brow_r = reinterpret_cast<int32_t*>(scratch + S.brow_r);
-    d.flags = reinterpret_cast<int32_t*>(scratch + S.flags);
     return d;
 }
 

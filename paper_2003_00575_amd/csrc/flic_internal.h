@@ -11,14 +11,21 @@ namespace flic {
 // Pixels per workgroup tile held in LDS (range + union-find parent per pixel).
 constexpr int kTilePx = 8192;
 constexpr int kMaxSkip = 8;
+// Run roots kept per 64-pixel row chunk in the compact run array; a chunk with
+// more runs keeps the rest in its label segment.
+constexpr int kRunHead = 16;
 
 // Per-scan descriptor as the kernels read it (device memory, or a kernel
 // argument for the single-scan path).
 //
 // Scratch (device memory owned by the library, per scan):
-//   masks   [H][chunks_per_row] pairs of uint64: bit x of .x marks the first
-//           pixel of a run (maximal row segment joined by direct horizontal
-//           edges) in that 64-pixel row chunk, bit x of .y a measurement.
+//   masks   [chunks_per_row][H] pairs of uint64 (chunk-major, so the rows of a
+//           strip are contiguous): bit x of .x marks the first pixel of a run
+//           (maximal row segment joined by direct horizontal edges) in that
+//           64-pixel row chunk, bit x of .y a measurement.
+//   runs    [chunks_per_row][H][kRunHead] uint16: tile-local root of the
+//           chunk's k-th run (k < kRunHead); runs k >= kRunHead keep theirs
+//           at position k of the chunk's label segment.
 //   parent  [H*W] int32, used only at tile-root positions: the global
 //           union-find of the tile components (written for every tile root
 //           by pass 1, joined by pass 2, read by pass 3).
@@ -26,22 +33,21 @@ constexpr int kMaxSkip = 8;
 //           first (side 0) and last (side 1) N columns of each tile.
 //   brow_v / brow_r  [tiles][2][N][tile_w]: the same for the first and last N
 //           rows; present only when the scan has more than one tile row.
-//   flags   one int32 written by pass 2: nonzero when some root pair was
-//           joined outside the compressed set, so pass 3 must walk to roots.
-// Between passes 1 and 3 the label array holds, at the start of each row
-// chunk, the global root of every run of that chunk in order.
+//           Pass 2 overwrites each used slot's range (bcol_v / brow_v) with
+//           the int32 final root of its provisional root, for pass 3.
+// Border slots outside the image part of a tile hold (NaN, -1).
 struct ScanDesc {
     const float* range;     // [H][W]
     int32_t* labels;        // [H][W]
     const float* cos_v;     // [N][H]
     const float* cos_h;     // [N][W]
     ulonglong2* masks;
+    uint16_t* runs;
     int32_t* parent;
     float* bcol_v;
     int32_t* bcol_r;
     float* brow_v;
     int32_t* brow_r;
-    int32_t* flags;
     int32_t H, W, N;
     float t2;               // fl32(T*T)
     int32_t tile_w;         // tile columns
@@ -64,7 +70,7 @@ inline int tile_h_for(int tile_w) { return kTilePx / tile_w; }
 // Scratch bytes one scan needs, and the sub-buffer offsets (each 256-byte
 // aligned) relative to the scan's scratch base.
 struct ScratchLayout {
-    size_t masks, parent, bcol_v, bcol_r, brow_v, brow_r, flags, total;
+    size_t masks, runs, parent, bcol_v, bcol_r, brow_v, brow_r, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -76,12 +82,12 @@ inline ScratchLayout scratch_layout(int H, int W, int N, int tile_w) {
     ScratchLayout L{};
     size_t o = 0;
     L.masks = o;  o = align256(o + (size_t)H * ((W + 63) / 64) * 16);
+    L.runs = o;   o = align256(o + (size_t)H * ((W + 63) / 64) * kRunHead * 2);
     L.parent = o; o = align256(o + (size_t)H * W * 4);
     L.bcol_v = o; o = align256(o + tiles * 2 * N * tile_h * 4);
     L.bcol_r = o; o = align256(o + tiles * 2 * N * tile_h * 4);
     L.brow_v = o; o = align256(o + (rows ? tiles * 2 * N * tile_w * 4 : 0));
     L.brow_r = o; o = align256(o + (rows ? tiles * 2 * N * tile_w * 4 : 0));
-    L.flags = o;  o = align256(o + 4);
     L.total = o;
     return L;
 }

@@ -8,32 +8,35 @@
 //     load   coalesced (float4 where aligned) copy of the tile's ranges into
 //            LDS, missing pixels replaced by NaN; the tile's slices of the
 //            angle tables staged in LDS as 2*cos.
-//     edges  per 64-pixel row chunk (one wavefront, lane = column) the edge
-//            test of Eq. (4) against the pixel k columns right and k rows
-//            down, k = 1..N, each turned into a 64-bit wavefront ballot.
-//     runs   the k = 1 horizontal ballot gives the row runs directly: every
-//            pixel's parent is the first pixel of its run in the chunk.
-//     union  only edges not already implied are joined in an LDS union-find
-//            (atomicMin hooking of the larger root under the smaller): an
-//            edge is implied when the same edge one pixel to the left exists
-//            and both of its ends continue into this edge's ends along a run,
-//            when a k-step horizontal edge stays inside a run, or when a
-//            k-step vertical edge is covered by k direct ones.
-//     output the chunk's run and measurement masks; at the start of the
-//            chunk's label row segment, the global root (tile component
-//            minimum) of each run in order; the range and root of the tile's
-//            border columns (and rows); parent[root] = root for every tile
-//            root.  No per-pixel label is written yet.
+//     edges  per 64-pixel row chunk (one wavefront, lane = column, 8 rows
+//            walked top-down) the edge test of Eq. (4) against the pixel k
+//            columns right and k rows up, k = 1..N, each turned into a 64-bit
+//            wavefront ballot.
+//     runs   the k = 1 horizontal ballot gives the row runs directly; a run
+//            whose head has a direct vertical edge takes the strip root above
+//            it as parent (a register and one lane shuffle), so every pixel's
+//            parent is its strip root.
+//     joins  only edges that may join two different trees go through an LDS
+//            union-find (atomicMin hooking of the larger root under the
+//            smaller): an edge is implied when the same edge one pixel to the
+//            left exists and both of its ends continue along runs, when a
+//            k-step horizontal edge stays inside a run, or when a k-step
+//            vertical edge is covered by k direct ones.  Strip roots are then
+//            compressed to their final roots.
+//     output the chunk's run and measurement masks, the tile-local root of
+//            each run (compact run array), parent[root] = root for every tile
+//            root, and the range and root of every border slot.  No per-pixel
+//            label is written yet.
 //   k_scan_merge   one workgroup per scan: tests the edges between tiles
 //            (tile columns including the 360-degree seam, tile rows) from the
 //            compact border arrays, prunes implied ones, deduplicates them to
-//            pairs of tile roots and joins those in the parent array; every
-//            joined root is then pointed at its final root.  A root only ever
-//            hooks under a smaller one, so a component's final root is its
-//            minimum linear index.
-//   k_relabel      one workgroup per tile: expands the run lists through the
-//            parent array into the final labels, one coalesced store per
-//            pixel.
+//            pairs of tile roots and joins those in the parent array, then
+//            writes every border slot's final root over its range.  A root
+//            only ever hooks under a smaller one, so a component's final root
+//            is its minimum linear index.
+//   k_relabel      one workgroup per tile: maps the tile's changed border
+//            roots to final roots in LDS and expands the run roots into the
+//            final labels, one coalesced store per pixel.
 //
 // The edge test is bit-identical to a scalar binary32 evaluation: contraction
 // is off for the whole file (the build checks the ISA has no fused
@@ -107,8 +110,9 @@ __device__ __forceinline__ int lds_load(const int* p) {
 }
 
 // Find with path halving (each visited node re-pointed at its grandparent),
-// which keeps the trees that concurrent joins build shallow for later finds.  atomicMin only ever moves a parent to an
-// ancestor (a smaller index of the same tree), so it is safe next to hooks.
+// which keeps the trees that concurrent joins build shallow for later finds.
+// atomicMin only ever moves a parent to an ancestor (a smaller index of the
+// same tree), so it is safe next to hooks.
 __device__ __forceinline__ int lds_find(int* par, int x) {
     int p = lds_load(&par[x]);
     while (p != x) {
@@ -438,16 +442,17 @@ void k_tile_label(BatchRef ref) {
     }
     __syncthreads();
 
-    // Output 1: per row chunk, the run / measurement masks, the global root
-    // of each run at the start of the chunk's label segment, and
-    // parent[root] = root for every tile root.
+    // Output 1: per row chunk, the run / measurement masks, the tile-local
+    // root of each run (compact run array, overflow in the chunk's label
+    // segment), and parent[root] = root for every tile root.
     const int base = r0 * W + c0;
     const bool chunk_in = ch * 64 < tw;                  // chunk lies in the image
     const int rows = chunk_in ? max(0, min(kRowsPerWave, th - R0)) : 0;
     const gptr<unsigned> mask_words = global(reinterpret_cast<unsigned*>(d.masks));
+    const gptr<uint16_t> runs = global(d.runs);
     const gptr<int> labels = global(d.labels);
     const gptr<int> parent = global(d.parent);
-    const unsigned mbase = (r0 + R0) * d.chunks_per_row + c0 / 64 + ch;
+    const unsigned mrow = (c0 / 64 + ch) * H + r0 + R0;   // chunk-major row index of the strip
     const unsigned lbase = base + R0 * W + ch * 64;
     // final roots of the strip's run heads: two reads (head -> strip root ->
     // final root), the 8 rows' reads issued together
@@ -471,17 +476,23 @@ void k_tile_label(BatchRef ref) {
         words = lane_bit(1ull << (4 * j + 3)) ? (unsigned)(vmask >> 32) : words;
         if (head && j < rows) {
             const unsigned i = (R0 + j) * TW + c, root = node[j];
-            const unsigned groot = base + (root / TW) * W + (root % TW);
-            labels[lbase + j * W + __popcll(starts & below)] = groot;
-            if (root == i) parent[groot] = groot;
+            const int k = __popcll(starts & below);      // run index in the chunk
+            if (k < kRunHead)
+                runs[(mrow + j) * kRunHead + k] = (uint16_t)root;
+            else
+                labels[lbase + j * W + k] = root;
+            if (root == i) {
+                const unsigned groot = base + (root / TW) * W + (root % TW);
+                parent[groot] = groot;
+            }
         }
     }
-    if (lane < 4 * rows)
-        mask_words[4 * (mbase + (lane >> 2) * d.chunks_per_row) + (lane & 3)] = words;
+    if (lane < 4 * rows) mask_words[4 * mrow + lane] = words;
 
     // Output 2: range and global root of the border columns (and rows), one
     // thread per border slot, contiguous along the border.  The slot index is
-    // the offset within the tile's block.
+    // the offset within the tile's block; a slot outside the image part of the
+    // tile gets (NaN, -1).
     const gptr<float> bcol_v = global(d.bcol_v) + (unsigned)(tile * kColItems);
     const gptr<int> bcol_r = global(d.bcol_r) + (unsigned)(tile * kColItems);
     const gptr<float> brow_v = global(d.brow_v) + (unsigned)(tile * kRowItems);
@@ -490,8 +501,9 @@ void k_tile_label(BatchRef ref) {
     for (int u = 0; u < kSlotRounds; ++u) {
         const int it = threadIdx.x + u * kLabelThreads;
         int rr, cc;
-        if (it >= n_slots || !border_slot<TW, N>(it, tw, th, rr, cc)) continue;
-        const int p = par[rr * TW + cc];
+        if (it >= n_slots) continue;
+        const bool in = border_slot<TW, N>(it, tw, th, rr, cc);   // else: marked empty
+        const int p = in ? par[rr * TW + cc] : -1;
         int groot = -1;
         if (p >= 0) {
             const unsigned root = par[p];                // strip root -> final root
@@ -723,7 +735,29 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
         if (ra != a) par[a] = ra;
         if (ra != b) par[b] = ra;
     }
-    if (threadIdx.x == 0) *d.flags = overflow;
+    __syncthreads();
+
+    // The final root of every border slot, written over the slot's range
+    // (not needed any more): pass 3 then needs no parent lookups.  After the
+    // compression a tile root's parent is final, unless a pair was joined
+    // outside the set.
+    const bool walk = overflow != 0;
+    {
+        const int n = n_tiles * 2 * N * TH;
+        int* fin = reinterpret_cast<int*>(d.bcol_v);
+        for (int i = threadIdx.x; i < n; i += kMergeThreads) {
+            const int r = d.bcol_r[i];
+            if (r >= 0) fin[i] = walk ? wg_find(par, r) : wg_load(&par[r]);
+        }
+    }
+    if (d.tiles_y > 1) {
+        const int n = n_tiles * 2 * N * TW;
+        int* fin = reinterpret_cast<int*>(d.brow_v);
+        for (int i = threadIdx.x; i < n; i += kMergeThreads) {
+            const int r = d.brow_r[i];
+            if (r >= 0) fin[i] = walk ? wg_find(par, r) : wg_load(&par[r]);
+        }
+    }
 }
 
 // ---- pass 3: run lists -> labels ---------------------------------------------
@@ -735,19 +769,13 @@ __device__ __forceinline__ uint64_t lane_word(uint64_t v, int j) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ int root_of(const int* par, int x) {
-    int p = par[x];
-    while (p != x) {
-        x = p;
-        p = par[x];
-    }
-    return x;
-}
-
-// One workgroup per tile, 16 rows of one 64-column chunk per wavefront: each
-// wavefront issues the masks of all its rows (one per lane) and the heads of
-// their run lists at once, so two dependent memory round trips cover 1024
-// pixels.
+// One workgroup per tile, 16 rows of one 64-column chunk per wavefront.  Only
+// roots that touch a tile border can change in pass 2, and the border slots
+// hold them with their final roots: the workgroup puts the changed ones into
+// an LDS map indexed by tile-local root; every other run keeps its own root.
+// Each wavefront issues the masks of all its rows (one per lane), the heads
+// of their run lists and its share of the border slots at once, so one
+// memory round trip covers the tile.
 constexpr int kRelabelRows = 16;
 constexpr int kRelabelThreads = kTilePx / kRelabelRows;
 
@@ -756,7 +784,8 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
     constexpr int CH = TW / 64;
     static_assert(CH * TH == (kRelabelThreads / 64) * kRelabelRows, "one strip per wavefront");
-    constexpr int kListHead = 16;                 // run-list entries loaded up front
+    static_assert(kRelabelRows == 16 && kRunHead == 16, "two 256-byte run loads per strip");
+    __shared__ int fin[kTilePx];                  // tile-local root -> final root, or -1
     ScanDesc d;
     int tile;
     locate(ref, blockIdx.x, d, tile);
@@ -764,46 +793,77 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     const int c0 = tx * TW, r0 = ty * TH;
     const int tw = min(TW, d.W - c0), th = min(TH, d.H - r0);
     const int W = d.W;
+    const unsigned base = r0 * W + c0;
     const int lane = threadIdx.x & 63, wave = wave_id();
     const int ch = wave % CH, R0 = (wave / CH) * kRelabelRows;
     const int c = ch * 64 + lane;
-    if (ch * 64 >= tw || R0 >= th) return;
-    const int rows = min(kRelabelRows, th - R0);
+    const bool strip_in = ch * 64 < tw && R0 < th;
+    const int rows = strip_in ? min(kRelabelRows, th - R0) : 0;
     const uint64_t le = lanes_le(lane);
     const bool col_in = c < tw;
     const gptr<const u64x2> masks = global(reinterpret_cast<const u64x2*>(d.masks));
+    const gptr<const unsigned> runs = global(reinterpret_cast<const unsigned*>(d.runs));
     const gptr<int> labels = global(d.labels);
-    const gptr<const int> parent = global(static_cast<const int*>(d.parent));
-    const unsigned mbase = (r0 + R0) * d.chunks_per_row + c0 / 64 + ch;
-    const unsigned lbase = (r0 + R0) * W + c0 + ch * 64;
-    // all loads of the strip first: lane j holds row j's masks; every row's
-    // first kListHead run roots (enough for most chunks) ...
-    const u64x2 mine = lane < rows ? masks[mbase + lane * d.chunks_per_row] : u64x2{0, 0};
-    int listed[kRelabelRows];
+    const unsigned mrow = (c0 / 64 + ch) * d.H + r0 + R0;   // chunk-major row index of the strip
+    const unsigned lbase = base + R0 * W + ch * 64;
+
+    for (int i = threadIdx.x; i < kTilePx; i += kRelabelThreads) fin[i] = -1;
+    __syncthreads();
+
+    // all loads first: lane j holds row j's masks; the strip's compact run
+    // roots (two uint16 per lane: rows 0-7 in ra, rows 8-15 in rb); the
+    // border slots' roots
+    const u64x2 mine = lane < rows ? masks[mrow + lane] : u64x2{0, 0};
+    const unsigned ra = (lane >> 3) < rows ? runs[mrow * (kRunHead / 2) + lane] : 0;
+    const unsigned rb = 8 + (lane >> 3) < rows ? runs[mrow * (kRunHead / 2) + 64 + lane] : 0;
+    const int n_col = 2 * d.N * TH, n_row = d.tiles_y > 1 ? 2 * d.N * TW : 0;
+    // border slots: provisional root and (written by pass 2 over the range)
+    // final root
+    const gptr<const int> bcol_r = global(static_cast<const int*>(d.bcol_r)) + (unsigned)(tile * n_col);
+    const gptr<const int> brow_r = global(static_cast<const int*>(d.brow_r)) + (unsigned)(tile * 2 * d.N * TW);
+    const gptr<const int> bcol_f = global(reinterpret_cast<const int*>(d.bcol_v)) + (unsigned)(tile * n_col);
+    const gptr<const int> brow_f = global(reinterpret_cast<const int*>(d.brow_v)) + (unsigned)(tile * 2 * d.N * TW);
+    constexpr int kSlotRounds = (2 * kMaxSkip * (TH + TW) + kRelabelThreads - 1) / kRelabelThreads;
+    int sroot[kSlotRounds], sfin[kSlotRounds];
 #pragma unroll
-    for (int j = 0; j < kRelabelRows; ++j)
-        listed[j] = (j < rows && col_in && lane < kListHead) ? labels[lbase + j * W + lane] : -1;
-    // ... then, row by row: the rest of the list for the rare chunk with more
-    // runs, every pixel's run root and its final root
-    int out[kRelabelRows];
+    for (int u = 0; u < kSlotRounds; ++u) {
+        const int it = threadIdx.x + u * kRelabelThreads;
+        const bool col = it < n_col, row = !col && it < n_col + n_row;
+        sroot[u] = col ? bcol_r[it] : (row ? brow_r[it - n_col] : -1);
+        sfin[u] = col ? bcol_f[it] : (row ? brow_f[it - n_col] : -1);
+    }
+    // border roots that changed -> the LDS map (every slot of a root writes
+    // the same value)
+#pragma unroll
+    for (int u = 0; u < kSlotRounds; ++u) {
+        const int g = sroot[u];
+        if (g >= 0 && sfin[u] != g) {
+            const unsigned o = g - base;
+            fin[(o / W) * TW + (o % W)] = sfin[u];
+        }
+    }
+    __syncthreads();
+
+    // ... then, row by row: every pixel's run root (from the run array, or
+    // for runs beyond the first kRunHead of a chunk from its label segment)
+    // and its final root, one store per pixel
 #pragma unroll
     for (int j = 0; j < kRelabelRows; ++j) {
         const uint64_t starts = lane_word(mine.x, j), valid = lane_word(mine.y, j);
-        const int n = __popcll(starts);
-        if (n > kListHead && lane >= kListHead && lane < n) listed[j] = labels[lbase + j * W + lane];
-        const int run = __popcll(starts & le) - 1;
-        const int groot = __shfl(listed[j], run < 0 ? 0 : run);
-        out[j] = lane_bit(valid) ? parent[groot] : -1;
+        const int run = max(__popcll(starts & le) - 1, 0);
+        const unsigned pair = __shfl(j < 8 ? ra : rb, (j % 8) * 8 + ((run >> 1) & 7));
+        unsigned local = (run & 1) ? pair >> 16 : pair & 0xffff;
+        if (__popcll(starts) > kRunHead) {           // rare: a chunk with many runs
+            const int n = __popcll(starts);
+            const int more = (lane >= kRunHead && lane < n) ? labels[lbase + j * W + lane] : 0;
+            const unsigned far = (unsigned)__shfl(more, run);
+            if (run >= kRunHead) local = far;
+        }
+        local &= kTilePx - 1;
+        const int f = fin[local];
+        const int out = lane_bit(valid) ? (f >= 0 ? f : (int)(base + (local / TW) * W + (local % TW))) : -1;
+        if (j < rows && col_in) labels[lbase + j * W + lane] = out;
     }
-    if (*d.flags) {                                  // some roots were joined uncompressed
-#pragma unroll
-        for (int j = 0; j < kRelabelRows; ++j)
-            if (out[j] >= 0) out[j] = root_of(d.parent, out[j]);
-    }
-    // ... then the labels (the run lists are overwritten only now)
-#pragma unroll
-    for (int j = 0; j < kRelabelRows; ++j)
-        if (j < rows && col_in) labels[lbase + j * W + lane] = out[j];
 }
 
 template <int TW, int N>
