@@ -478,16 +478,16 @@ void k_tile_label(BatchRef ref) {
             const unsigned i = (R0 + j) * TW + c, root = node[j];
             const int k = __popcll(starts & below);      // run index in the chunk
             if (k < kRunHead)
-                runs[(mrow + j) * kRunHead + k] = (uint16_t)root;
+                (runs + (mrow + j) * kRunHead)[k] = (uint16_t)root;
             else
-                labels[lbase + j * W + k] = root;
+                (labels + (lbase + j * W))[k] = root;
             if (root == i) {
                 const unsigned groot = base + (root / TW) * W + (root % TW);
                 parent[groot] = groot;
             }
         }
     }
-    if (lane < 4 * rows) mask_words[4 * mrow + lane] = words;
+    if (lane < 4 * rows) (mask_words + 4 * mrow)[lane] = words;
 
     // Output 2: range and global root of the border columns (and rows), one
     // thread per border slot, contiguous along the border.  The slot index is
@@ -849,20 +849,24 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     // and its final root, one store per pixel
 #pragma unroll
     for (int j = 0; j < kRelabelRows; ++j) {
+        const gptr<int> row = global(d.labels) + ((size_t)(r0 + R0 + j) * W + c0 + ch * 64);   // scalar base
         const uint64_t starts = lane_word(mine.x, j), valid = lane_word(mine.y, j);
-        const int run = max(__popcll(starts & le) - 1, 0);
-        const unsigned pair = __shfl(j < 8 ? ra : rb, (j % 8) * 8 + ((run >> 1) & 7));
-        unsigned local = (run & 1) ? pair >> 16 : pair & 0xffff;
+        // run index: starts at or below this lane, minus one
+        const int run = __builtin_amdgcn_mbcnt_hi((unsigned)(starts >> 32),
+                            __builtin_amdgcn_mbcnt_lo((unsigned)starts, lane_bit(starts) ? 0u : ~0u));
+        const unsigned pair = __builtin_amdgcn_ds_bpermute(
+            (((j % 8) * 8 + ((run >> 1) & 7)) << 2), (int)(j < 8 ? ra : rb));
+        unsigned local = (pair >> ((run & 1) << 4)) & 0xffffu;
         if (__popcll(starts) > kRunHead) {           // rare: a chunk with many runs
             const int n = __popcll(starts);
-            const int more = (lane >= kRunHead && lane < n) ? labels[lbase + j * W + lane] : 0;
-            const unsigned far = (unsigned)__shfl(more, run);
+            const int more = (lane >= kRunHead && lane < n) ? row[lane] : 0;
+            const unsigned far = (unsigned)__builtin_amdgcn_ds_bpermute((run & 63) << 2, more);
             if (run >= kRunHead) local = far;
         }
         local &= kTilePx - 1;
         const int f = fin[local];
         const int out = lane_bit(valid) ? (f >= 0 ? f : (int)(base + (local / TW) * W + (local % TW))) : -1;
-        if (j < rows && col_in) labels[lbase + j * W + lane] = out;
+        if (j < rows && col_in) row[lane] = out;
     }
 }
 
