@@ -360,12 +360,12 @@ void k_tile_label(BatchRef ref) {
         const bool up = lane_bit(link);
         const int got = __shfl(up ? above : kNoRoot, head);
         const int root = got != kNoRoot ? got : r * TW + ch * 64 + head;
-        par[r * TW + c] = valid ? root : -1;
+        par[r * TW + c] = root;                           // (never read for a missing pixel)
         if (up && above != root) t |= 2u;                // may join another tree above
         if (valid && head == lane) heads |= 1u << j;
         if (valid && head == lane && got == kNoRoot) sroots |= 1u << j;   // a new strip root
         if (valid) valids |= 1u << j;
-        above = valid ? root : kNoRoot;
+        above = root;                                     // read only below a measurement
         // materialise this row's per-lane results here: otherwise the compiler
         // sinks them to their uses after the barrier and keeps the 64-bit
         // masks alive (spilled) instead
@@ -503,9 +503,10 @@ void k_tile_label(BatchRef ref) {
         int rr, cc;
         if (it >= n_slots) continue;
         const bool in = border_slot<TW, N>(it, tw, th, rr, cc);   // else: marked empty
-        const int p = in ? par[rr * TW + cc] : -1;
+        const bool measured = in && slot_v[u] == slot_v[u];
+        const int p = measured ? par[rr * TW + cc] : 0;
         int groot = -1;
-        if (p >= 0) {
+        if (measured) {
             const unsigned root = par[p];                // strip root -> final root
             groot = base + (root / TW) * W + (root % TW);
         }
