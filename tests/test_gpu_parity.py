@@ -194,3 +194,36 @@ def test_batched_mixed_skip_depths_and_stream(flic):
     st.synchronize()
     for i, (s, d) in enumerate(zip(scans, devs)):
         assert_same(d.labels.cpu().numpy(), oracle.cluster_scan(s), f"scan {i}")
+
+
+def _border_pairs_scan(H=128, W=16384, N=3, seg=4, tile_w=64):
+    """Every even row holds a short segment across every tile-column border
+    (and the 360-degree seam), each row at its own range 1 m from the next, so
+    no vertical or skip edge joins two rows: about (H/2) * (W/tile_w) distinct
+    pairs of tile roots meet in the scan merge, twice its 8192-entry pair set,
+    and the pairs that find no slot take the direct join (and the final-root
+    walk that follows it)."""
+    img = np.zeros((H, W), np.float32)
+    for r in range(0, H, 2):
+        for b in range(0, W, tile_w):
+            cols = np.arange(b - seg, b + seg) % W
+            img[r, cols] = 10.0 + r
+    phi = synth.elevations(H, 2.0, -24.8)
+    cos_v, cos_h = synth.make_tables(phi, W, N)
+    return synth.Scan(img, cos_v, cos_h, 0.5, N, None, 0)
+
+
+def test_merge_pair_set_overflow(flic):
+    scan = _border_pairs_scan()
+    want = oracle.cluster_scan(scan)
+    # every segment is one component spanning two tiles
+    assert len(np.unique(want[want >= 0])) == (scan.range_img.shape[0] // 2) * (scan.range_img.shape[1] // 64)
+    assert_same(run_gpu(flic, scan, tile_w=64), want, "pair-set overflow")
+    ctx = flic.Context(0)
+    ctx.set_tile_width(64)
+    d = flic.to_device(scan)
+    plan = ctx.plan([d])
+    plan.relaunch()
+    torch.cuda.synchronize()
+    assert_same(d.labels.cpu().numpy(), want, "pair-set overflow, plan")
+    plan.close()
