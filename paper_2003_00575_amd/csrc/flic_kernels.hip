@@ -24,16 +24,15 @@
 //            vertical edge is covered by k direct ones.  Strip roots are then
 //            compressed to their final roots.
 //     output the chunk's run and measurement masks, the tile-local root of
-//            each run (compact run array), parent[root] = root for every tile
-//            root, and the range and root of every border slot.  No per-pixel
-//            label is written yet.
-//   k_scan_merge   one workgroup per scan: tests the edges between tiles
-//            (tile columns including the 360-degree seam, tile rows) from the
-//            compact border arrays, prunes implied ones, deduplicates them to
-//            pairs of tile roots and joins those in the parent array, then
-//            writes every border slot's final root over its range.  A root
-//            only ever hooks under a smaller one, so a component's final root
-//            is its minimum linear index.
+//            each run (compact run array), and the range and root of every
+//            border slot.  No per-pixel label is written yet.
+//   k_scan_merge   one workgroup per scan: enters the border slots' roots
+//            into an LDS node table, tests the edges between tiles (tile
+//            columns including the 360-degree seam, tile rows) from the
+//            compact border arrays, prunes implied ones and joins the rest in
+//            an LDS union-find, then writes every border slot's final root
+//            over its range.  A root only ever hooks under a smaller one, so
+//            a component's final root is its minimum linear index.
 //   k_relabel      one workgroup per tile: maps the tile's changed border
 //            roots to final roots in LDS and expands the run roots into the
 //            final labels, one coalesced store per pixel.
@@ -444,14 +443,13 @@ void k_tile_label(BatchRef ref) {
 
     // Output 1: per row chunk, the run / measurement masks, the tile-local
     // root of each run (compact run array, overflow in the chunk's label
-    // segment), and parent[root] = root for every tile root.
+    // segment).
     const int base = r0 * W + c0;
     const bool chunk_in = ch * 64 < tw;                  // chunk lies in the image
     const int rows = chunk_in ? max(0, min(kRowsPerWave, th - R0)) : 0;
     const gptr<unsigned> mask_words = global(reinterpret_cast<unsigned*>(d.masks));
     const gptr<uint16_t> runs = global(d.runs);
     const gptr<int> labels = global(d.labels);
-    const gptr<int> parent = global(d.parent);
     const unsigned mrow = (c0 / 64 + ch) * H + r0 + R0;   // chunk-major row index of the strip
     const unsigned lbase = base + R0 * W + ch * 64;
     // final roots of the strip's run heads: two reads (head -> strip root ->
@@ -475,16 +473,12 @@ void k_tile_label(BatchRef ref) {
         words = lane_bit(1ull << (4 * j + 2)) ? (unsigned)vmask : words;
         words = lane_bit(1ull << (4 * j + 3)) ? (unsigned)(vmask >> 32) : words;
         if (head && j < rows) {
-            const unsigned i = (R0 + j) * TW + c, root = node[j];
+            const unsigned root = node[j];
             const int k = __popcll(starts & below);      // run index in the chunk
             if (k < kRunHead)
                 (runs + (mrow + j) * kRunHead)[k] = (uint16_t)root;
             else
                 (labels + (lbase + j * W))[k] = root;
-            if (root == i) {
-                const unsigned groot = base + (root / TW) * W + (root % TW);
-                parent[groot] = groot;
-            }
         }
     }
     if (lane < 4 * rows) (mask_words + 4 * mrow)[lane] = words;
@@ -522,19 +516,29 @@ void k_tile_label(BatchRef ref) {
 
 // ---- pass 2: edges between tiles, one workgroup per scan ------------------
 //
-// Only this workgroup touches the scan's parent array during the pass, so
-// the union-find needs no cross-workgroup coherence: atomics and loads are
-// workgroup-scope (performed at / read from the L2 of this CU's XCD).
+// The nodes are the tile roots that appear in the scan's border slots.  Each
+// is entered into an LDS hash table (key: its global index; the table
+// position is the node), the crossing edges join nodes in an LDS union-find
+// whose root is always the node with the smallest key, and every border slot
+// then gets the key of its node's root -- the minimum linear index of its
+// component -- written over its range.  A scan whose border roots do not fit
+// the table takes the same steps on the scan's parent array in global memory
+// (workgroup-scope atomics: only this workgroup touches it), with an LDS hash
+// set dropping repeated root pairs.
+//
 // Border values and roots come from the compact arrays written by pass 1;
 // lane = row along a tile column border, lane = column along a tile row
 // border.  An edge is skipped when the same edge one row up (one column
 // left) exists and both its ends continue into this edge's ends by a direct
-// edge inside their tiles.  Remaining edges become (root, root) pairs; each
-// wavefront drops repeats and appends the rest to an LDS list, which is then
-// joined in parallel and compressed.
+// edge inside their tiles.
 
 constexpr int kMergeThreads = 1024;
-constexpr int kSetCap = 8192;                 // LDS hash set of (root, root) pairs
+constexpr int kSlotBatch = 8;                 // border-slot loads in flight per thread
+constexpr int kNodeBits = 13;
+constexpr int kNodeCap = 1 << kNodeBits;      // LDS node table (global root -> node)
+constexpr int kNodeProbe = 64;
+constexpr int kNoKey = -1;
+constexpr int kSetCap = 8192;                 // global path: LDS hash set of (root, root) pairs
 constexpr int kMaxProbe = 32;
 constexpr unsigned long long kEmpty = ~0ull;
 
@@ -587,22 +591,79 @@ __device__ __forceinline__ void push_pairs(bool act, int a, int b, unsigned long
     *overflow = 1;
 }
 
-template <int TW, int N>
-__global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
+// Enter the (a, b) root pair of an active lane into the LDS hash set; false
+// when it finds no slot within kMaxProbe probes.
+__device__ __forceinline__ bool set_insert(unsigned long long* set, int a, int b) {
+    const unsigned long long key = ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
+    unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 40) & (kSetCap - 1);
+    for (int probe = 0; probe < kMaxProbe; ++probe) {
+        const unsigned long long old = atomicCAS(&set[h], kEmpty, key);
+        if (old == kEmpty || old == key) return true;
+        h = (h + 1) & (kSetCap - 1);
+    }
+    return false;
+}
+
+// ---- LDS node table and union-find over its positions ----
+
+__device__ __forceinline__ unsigned node_hash(int key) {
+    return ((unsigned)key * 2654435761u) >> (32 - kNodeBits);
+}
+
+// Enter a global root; its node, or -1 when no position is free within
+// kNodeProbe probes.
+__device__ __forceinline__ int node_insert(int* keys, int key) {
+    unsigned h = node_hash(key);
+    for (int p = 0; p < kNodeProbe; ++p) {
+        const int old = atomicCAS(&keys[h], kNoKey, key);
+        if (old == kNoKey || old == key) return (int)h;
+        h = (h + 1) & (kNodeCap - 1);
+    }
+    return -1;
+}
+
+// Node of a root that was entered (bounded scan of the probe sequence).
+__device__ __forceinline__ int node_of(const int* keys, int key) {
+    unsigned h = node_hash(key);
+    for (int p = 0; p < kNodeProbe && lds_load(&keys[h]) != key; ++p) h = (h + 1) & (kNodeCap - 1);
+    return (int)h;
+}
+
+// Find with path halving.  A non-root entry only ever moves to an ancestor,
+// and hooks change only roots, so the halving stores need no atomics.
+__device__ __forceinline__ int node_find(int* npar, int x) {
+    int p = lds_load(&npar[x]);
+    while (p != x) {
+        const int g = lds_load(&npar[p]);
+        if (g == p) return p;
+        npar[x] = g;
+        x = g;
+        p = lds_load(&npar[x]);
+    }
+    return x;
+}
+
+// Join two sets: the root with the larger key is hooked under the other
+// (compare-and-swap on a root), so every set's root holds its smallest key.
+__device__ void node_unite(int* npar, const int* keys, int a, int b) {
+    for (;;) {
+        a = node_find(npar, a);
+        b = node_find(npar, b);
+        if (a == b) return;
+        if (keys[a] > keys[b]) { const int t = a; a = b; b = t; }
+        if (atomicCAS(&npar[b], b, a) == b) return;
+    }
+}
+
+// Every crossing edge between two tiles of the scan that is not implied:
+// on_edge(need, root_a, root_b) is called by every lane of a wavefront, with
+// need set on the lanes that hold such an edge.
+template <int TW, int N, typename F>
+__device__ __forceinline__ void for_crossing_edges(const ScanDesc& d, int lane, int wave, F&& on_edge) {
     constexpr int TH = kTilePx / TW;
     constexpr int kWaves = kMergeThreads / 64;
-    __shared__ unsigned long long set[kSetCap];
-    __shared__ int overflow;
-
-    const ScanDesc d = ref.descs ? ref.descs[blockIdx.x] : ref.one;
     const int W = d.W, H = d.H;
     const float t2 = d.t2;
-    const int lane = threadIdx.x & 63, wave = wave_id();
-    int* par = d.parent;
-    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) set[i] = kEmpty;
-    if (threadIdx.x == 0) overflow = 0;
-    __syncthreads();
-
     // tile column borders: item = (tile, 64-row chunk); the tile's last N
     // columns against the next N columns to its right (mod W)
     constexpr int RCH = (TH + 63) / 64;
@@ -660,7 +721,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
                 const uint64_t E = ballot(e);
                 const uint64_t V = ballot(us[j] && ut[m]);
                 const bool need = lane_bit(E & ~((E << 1) & V));
-                push_pairs(need, rsrc[j], rtgt[m], set, par, &overflow);
+                on_edge(need, rsrc[j], rtgt[m]);
             }
         }
     }
@@ -716,13 +777,102 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
                     const uint64_t E = ballot(e);
                     const uint64_t L = ballot(ls[j] && lt[m]);
                     const bool need = lane_bit(E & ~((E << 1) & L));
-                    push_pairs(need, rsrc[j], rtgt[m], set, par, &overflow);
+                    on_edge(need, rsrc[j], rtgt[m]);
                 }
             }
         }
     }
+}
+
+// Root of border slot i of the scan (column slots first, then row slots).
+__device__ __forceinline__ int slot_root(const ScanDesc& d, int i, int n_col) {
+    return i < n_col ? d.bcol_r[i] : d.brow_r[i - n_col];
+}
+
+__device__ __forceinline__ void set_slot_final(const ScanDesc& d, int i, int n_col, int f) {
+    if (i < n_col)
+        reinterpret_cast<int*>(d.bcol_v)[i] = f;
+    else
+        reinterpret_cast<int*>(d.brow_v)[i - n_col] = f;
+}
+
+template <int TW, int N>
+__global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
+    constexpr int TH = kTilePx / TW;
+    __shared__ int keys[kNodeCap];             // node -> global root (kNoKey: free)
+    __shared__ int npar[kNodeCap];             // union-find over nodes
+    __shared__ unsigned long long set[kSetCap];
+    __shared__ int overflow;
+
+    const ScanDesc d = ref.descs ? ref.descs[blockIdx.x] : ref.one;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int n_tiles = d.tiles_x * d.tiles_y;
+    const int n_col = n_tiles * 2 * N * TH;
+    const int n_slots = n_col + (d.tiles_y > 1 ? n_tiles * 2 * N * TW : 0);
+    for (int i = threadIdx.x; i < kNodeCap; i += kMergeThreads) {
+        keys[i] = kNoKey;
+        npar[i] = i;
+    }
+    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) set[i] = kEmpty;
+    if (threadIdx.x == 0) overflow = 0;
     __syncthreads();
 
+    // every border root becomes a node (kSlotBatch slot loads in flight per
+    // thread); every needed crossing edge becomes a distinct root pair
+    for (int i0 = threadIdx.x; i0 < n_slots; i0 += kSlotBatch * kMergeThreads) {
+        int r[kSlotBatch];
+#pragma unroll
+        for (int u = 0; u < kSlotBatch; ++u) {
+            const int i = i0 + u * kMergeThreads;
+            r[u] = i < n_slots ? slot_root(d, i, n_col) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kSlotBatch; ++u)
+            if (r[u] >= 0 && node_insert(keys, r[u]) < 0) overflow = 1;
+    }
+    for_crossing_edges<TW, N>(d, lane, wave, [&](bool need, int a, int b) {
+        if (need && !set_insert(set, a, b)) overflow = 1;
+    });
+    __syncthreads();
+
+    if (!overflow) {
+        for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) {
+            const unsigned long long key = set[i];
+            if (key != kEmpty)
+                node_unite(npar, keys, node_of(keys, (int)(key >> 32)), node_of(keys, (int)(key & 0xffffffffu)));
+        }
+        __syncthreads();
+        for (int i0 = threadIdx.x; i0 < n_slots; i0 += kSlotBatch * kMergeThreads) {
+            int r[kSlotBatch];
+#pragma unroll
+            for (int u = 0; u < kSlotBatch; ++u) {
+                const int i = i0 + u * kMergeThreads;
+                r[u] = i < n_slots ? slot_root(d, i, n_col) : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kSlotBatch; ++u)
+                if (r[u] >= 0)
+                    set_slot_final(d, i0 + u * kMergeThreads, n_col, keys[node_find(npar, node_of(keys, r[u]))]);
+        }
+        return;
+    }
+
+    // Too many border roots or root pairs for LDS: the parent array in global
+    // memory.  Every border root starts as its own parent; repeated pairs are
+    // dropped by the set, and a pair that finds no slot is joined at once.
+    int* par = d.parent;
+    __syncthreads();                                 // everyone has read the flag
+    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) set[i] = kEmpty;
+    for (int i = threadIdx.x; i < n_slots; i += kMergeThreads) {
+        const int r = slot_root(d, i, n_col);
+        if (r >= 0) par[r] = r;
+    }
+    if (threadIdx.x == 0) overflow = 0;
+    __syncthreads();
+    for_crossing_edges<TW, N>(d, lane, wave, [&](bool need, int a, int b) {
+        push_pairs(need, a, b, set, par, &overflow);
+    });
+    __syncthreads();
     for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) {
         const unsigned long long key = set[i];
         if (key != kEmpty) wg_unite(par, (int)(key >> 32), (int)(key & 0xffffffffu));
@@ -737,27 +887,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
         if (ra != b) par[b] = ra;
     }
     __syncthreads();
-
-    // The final root of every border slot, written over the slot's range
-    // (not needed any more): pass 3 then needs no parent lookups.  After the
-    // compression a tile root's parent is final, unless a pair was joined
-    // outside the set.
+    // After the compression a root's parent is final, unless a pair was
+    // joined outside the set.
     const bool walk = overflow != 0;
-    {
-        const int n = n_tiles * 2 * N * TH;
-        int* fin = reinterpret_cast<int*>(d.bcol_v);
-        for (int i = threadIdx.x; i < n; i += kMergeThreads) {
-            const int r = d.bcol_r[i];
-            if (r >= 0) fin[i] = walk ? wg_find(par, r) : wg_load(&par[r]);
-        }
-    }
-    if (d.tiles_y > 1) {
-        const int n = n_tiles * 2 * N * TW;
-        int* fin = reinterpret_cast<int*>(d.brow_v);
-        for (int i = threadIdx.x; i < n; i += kMergeThreads) {
-            const int r = d.brow_r[i];
-            if (r >= 0) fin[i] = walk ? wg_find(par, r) : wg_load(&par[r]);
-        }
+    for (int i = threadIdx.x; i < n_slots; i += kMergeThreads) {
+        const int r = slot_root(d, i, n_col);
+        if (r >= 0) set_slot_final(d, i, n_col, walk ? wg_find(par, r) : wg_load(&par[r]));
     }
 }
 
@@ -800,13 +935,10 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     const int c = ch * 64 + lane;
     const bool strip_in = ch * 64 < tw && R0 < th;
     const int rows = strip_in ? min(kRelabelRows, th - R0) : 0;
-    const uint64_t le = lanes_le(lane);
     const bool col_in = c < tw;
     const gptr<const u64x2> masks = global(reinterpret_cast<const u64x2*>(d.masks));
     const gptr<const unsigned> runs = global(reinterpret_cast<const unsigned*>(d.runs));
-    const gptr<int> labels = global(d.labels);
     const unsigned mrow = (c0 / 64 + ch) * d.H + r0 + R0;   // chunk-major row index of the strip
-    const unsigned lbase = base + R0 * W + ch * 64;
 
     for (int i = threadIdx.x; i < kTilePx; i += kRelabelThreads) fin[i] = -1;
     __syncthreads();
