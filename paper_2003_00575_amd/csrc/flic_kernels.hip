@@ -826,9 +826,13 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
             const int i = i0 + u * kMergeThreads;
             r[u] = i < n_slots ? slot_root(d, i, n_col) : -1;
         }
+        // consecutive slots (rows of one border column) mostly share a root:
+        // only the first lane of each run of equal roots enters it
 #pragma unroll
-        for (int u = 0; u < kSlotBatch; ++u)
-            if (r[u] >= 0 && node_insert(keys, r[u]) < 0) overflow = 1;
+        for (int u = 0; u < kSlotBatch; ++u) {
+            const int prev = __shfl_up(r[u], 1);
+            if (r[u] >= 0 && (lane == 0 || prev != r[u]) && node_insert(keys, r[u]) < 0) overflow = 1;
+        }
     }
     for_crossing_edges<TW, N>(d, lane, wave, [&](bool need, int a, int b) {
         if (need && !set_insert(set, a, b)) overflow = 1;
