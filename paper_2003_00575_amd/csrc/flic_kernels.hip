@@ -87,6 +87,14 @@ __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+// The 64-bit mask whose low word lane q holds and whose high word lane q + 1
+// holds, as a wave-uniform value.
+__device__ __forceinline__ uint64_t row_mask(unsigned v, int q) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)v, q);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)v, q + 1);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t lanes_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }
@@ -318,7 +326,10 @@ void k_tile_label(BatchRef ref) {
     // a strip border; bit k (1..N): k rows up; bit N+k-1 (k >= 2): k columns
     // right.  A bit is set only when the edge may join two different trees.
     uint32_t todo[kRowsPerWave];
-    uint32_t heads = 0, valids = 0, sroots = 0;          // bit j: row R0 + j
+    // Per row j, as 32-bit words held by single lanes: lane 4j + q holds word q
+    // of the row's (run starts, measurements) mask pair, lane 2j + q word q
+    // of its new strip roots (run heads that took no parent above).
+    unsigned words = 0, sroot_words = 0;
     int above = kNoRoot;                                 // strip root of the pixel above
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
@@ -361,14 +372,20 @@ void k_tile_label(BatchRef ref) {
         const int root = got != kNoRoot ? got : r * TW + ch * 64 + head;
         par[r * TW + c] = root;                           // (never read for a missing pixel)
         if (up && above != root) t |= 2u;                // may join another tree above
-        if (valid && head == lane) heads |= 1u << j;
-        if (valid && head == lane && got == kNoRoot) sroots |= 1u << j;   // a new strip root
-        if (valid) valids |= 1u << j;
+        const uint64_t vmask = ballot(valid);
+        const uint64_t starts = vmask & ~(h1 << 1);       // heads of the row's runs
+        const uint64_t sroots = starts & ~ballot(got != kNoRoot);
+        words = lane_bit(1ull << (4 * j + 0)) ? (unsigned)starts : words;
+        words = lane_bit(1ull << (4 * j + 1)) ? (unsigned)(starts >> 32) : words;
+        words = lane_bit(1ull << (4 * j + 2)) ? (unsigned)vmask : words;
+        words = lane_bit(1ull << (4 * j + 3)) ? (unsigned)(vmask >> 32) : words;
+        sroot_words = lane_bit(1ull << (2 * j + 0)) ? (unsigned)sroots : sroot_words;
+        sroot_words = lane_bit(1ull << (2 * j + 1)) ? (unsigned)(sroots >> 32) : sroot_words;
         above = root;                                     // read only below a measurement
         // materialise this row's per-lane results here: otherwise the compiler
         // sinks them to their uses after the barrier and keeps the 64-bit
         // masks alive (spilled) instead
-        asm volatile("" : "+v"(t), "+v"(heads), "+v"(valids), "+v"(sroots), "+v"(above));
+        asm volatile("" : "+v"(t), "+v"(words), "+v"(sroot_words), "+v"(above));
         todo[j] = t;
 #pragma unroll
         for (int k = N - 1; k >= 1; --k) {
@@ -426,7 +443,7 @@ void k_tile_label(BatchRef ref) {
         int count = 0;
 #pragma unroll
         for (int j = 0; j < kRowsPerWave; ++j) {
-            const bool sr = (sroots >> j) & 1;
+            const bool sr = lane_bit(row_mask(sroot_words, 2 * j));
             const uint64_t m = ballot(sr);
             if (sr) queue[count + __popcll(m & below)] = (R0 + j) * TW + c;
             count += __popcll(m);
@@ -457,21 +474,14 @@ void k_tile_label(BatchRef ref) {
     int node[kRowsPerWave];
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j)
-        node[j] = ((heads >> j) & 1) ? lds_load(&par[(R0 + j) * TW + c]) : 0;
+        node[j] = lane_bit(row_mask(words, 4 * j)) ? lds_load(&par[(R0 + j) * TW + c]) : 0;
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) node[j] = lds_load(&par[node[j]]);
-    // the masks of all rows in one store: lane 4j + q holds 32-bit word q of
-    // row j's (run starts, measurements) pair
-    unsigned words = 0;
+    // run roots; the masks of all rows in one store (words, built above)
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
-        const bool head = (heads >> j) & 1;
-        const uint64_t starts = ballot(head);
-        const uint64_t vmask = ballot((valids >> j) & 1);
-        words = lane_bit(1ull << (4 * j + 0)) ? (unsigned)starts : words;
-        words = lane_bit(1ull << (4 * j + 1)) ? (unsigned)(starts >> 32) : words;
-        words = lane_bit(1ull << (4 * j + 2)) ? (unsigned)vmask : words;
-        words = lane_bit(1ull << (4 * j + 3)) ? (unsigned)(vmask >> 32) : words;
+        const uint64_t starts = row_mask(words, 4 * j);
+        const bool head = lane_bit(starts);
         if (head && j < rows) {
             const unsigned root = node[j];
             const int k = __popcll(starts & below);      // run index in the chunk
