@@ -307,12 +307,13 @@ void k_tile_label(BatchRef ref) {
     // horizontal ballot (h1) and direct vertical ballot to the row above it
     // (v1; needed for the N-1 nearest rows only).
     float wv[N], ws[N];
-    uint64_t wh1[N], wv1[N];
+    uint64_t wh1[N], wv1[N], wvm[N];                      // wvm: measurement ballots
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         const int x = R0 - 1 - j;                         // >= -N
         wv[j] = at[x * RS];
         ws[j] = wv[j] * wv[j];
+        wvm[j] = ballot(wv[j] == wv[j]);
         const float right = at[x * RS + 1];
         wh1[j] = ballot(connected_sq(wv[j], ws[j], right, right * right, c2hk[0], t2));
         wv1[j] = 0;
@@ -336,34 +337,58 @@ void k_tile_label(BatchRef ref) {
         const int r = R0 + j;
         const float a = at[r * RS];
         const float sa = a * a;
-        uint64_t h1 = 0, v1 = 0, link = 0, chain = 0, run = 0;
         uint32_t t = 0;
+        // direct edges (k = 1)
+        const float b1 = at[r * RS + 1];
+        const uint64_t h1 = ballot(connected_sq(a, sa, b1, b1 * b1, c2hk[0], t2));
+        const uint64_t v1 = ballot(connected_sq(wv[0], ws[0], a, sa, c2v[0][r - 1 + N], t2));
+        const uint64_t vmask = ballot(a == a);
+        const uint64_t link = v1 & ~((v1 & h1 & wh1[0]) << 1);   // pruned direct vertical edges
+        if (CH > 1 && ch + 1 < CH && lane == 63 && (h1 >> 63)) t |= 1u;
+        // Skip edges (k >= 2) are tested only when some pair of measurements
+        // k apart is not already joined by direct edges (most rows): the row
+        // runs horizontally, the k-row vertical chain vertically.  The top
+        // lanes of a chunk with a chunk to its right always count.
+        constexpr uint64_t kTopLanes = ~0ull << (64 - N);
+        uint64_t need_h = (CH > 1 && ch + 1 < CH) ? (vmask & kTopLanes) : 0;
+        {
+            uint64_t run = h1;
 #pragma unroll
-        for (int k = 1; k <= N; ++k) {
-            const float b = at[r * RS + k];
-            const uint64_t hk = ballot(connected_sq(a, sa, b, b * b, c2hk[k - 1], t2));
-            const uint64_t vk = ballot(connected_sq(wv[k - 1], ws[k - 1], a, sa, c2v[k - 1][r - k + N], t2));
-            if (k == 1) {
-                h1 = hk;
-                v1 = vk;
-                chain = vk;
-                run = hk;
-                if (CH > 1 && ch + 1 < CH && lane == 63 && (h1 >> 63)) t |= 1u;
-            } else {
-                chain &= wv1[k - 2];
+            for (int k = 2; k <= N; ++k) {
+                run &= h1 >> (k - 1);
+                need_h |= vmask & (vmask >> k) & ~run;
+            }
+        }
+        if (need_h) {
+            uint64_t run = h1;
+#pragma unroll
+            for (int k = 2; k <= N; ++k) {
+                const float b = at[r * RS + k];
+                const uint64_t hk = ballot(connected_sq(a, sa, b, b * b, c2hk[k - 1], t2));
                 run &= h1 >> (k - 1);
                 const uint64_t hneed = hk & ~run & ~((hk & h1 & (h1 >> k)) << 1);
                 if (lane_bit(hneed)) t |= 1u << (N + k - 1);
             }
-            uint64_t vneed = vk & ~((vk & h1 & wh1[k - 1]) << 1);
-            if (k >= 2) {
-                vneed &= ~chain;
-                if (lane_bit(vneed)) t |= 1u << k;
-            } else {
-                link = vneed;                             // pruned direct vertical edges
+        }
+        uint64_t need_v = 0;
+        {
+            uint64_t chain = v1;
+#pragma unroll
+            for (int k = 2; k <= N; ++k) {
+                chain &= wv1[k - 2];
+                need_v |= vmask & wvm[k - 1] & ~chain;
             }
         }
-        const bool valid = a == a;
+        if (need_v) {
+            uint64_t chain = v1;
+#pragma unroll
+            for (int k = 2; k <= N; ++k) {
+                const uint64_t vk = ballot(connected_sq(wv[k - 1], ws[k - 1], a, sa, c2v[k - 1][r - k + N], t2));
+                chain &= wv1[k - 2];
+                const uint64_t vneed = vk & ~((vk & h1 & wh1[k - 1]) << 1) & ~chain;
+                if (lane_bit(vneed)) t |= 1u << k;
+            }
+        }
         const int head = 63 - __clzll(~(h1 << 1) & le);   // first pixel of the run
         // a run whose head has a (pruned) direct vertical edge takes the strip
         // root above the head; any other run is a new strip root
@@ -372,7 +397,6 @@ void k_tile_label(BatchRef ref) {
         const int root = got != kNoRoot ? got : r * TW + ch * 64 + head;
         par[r * TW + c] = root;                           // (never read for a missing pixel)
         if (up && above != root) t |= 2u;                // may join another tree above
-        const uint64_t vmask = ballot(valid);
         const uint64_t starts = vmask & ~(h1 << 1);       // heads of the row's runs
         const uint64_t sroots = starts & ~ballot(got != kNoRoot);
         words = lane_bit(1ull << (4 * j + 0)) ? (unsigned)starts : words;
@@ -393,11 +417,13 @@ void k_tile_label(BatchRef ref) {
             ws[k] = ws[k - 1];
             wh1[k] = wh1[k - 1];
             wv1[k] = wv1[k - 1];
+            wvm[k] = wvm[k - 1];
         }
         wv[0] = a;
         ws[0] = sa;
         wh1[0] = h1;
         wv1[0] = v1;
+        wvm[0] = vmask;
         // keep rows apart: interleaving them only raises scalar-register pressure
         __builtin_amdgcn_sched_barrier(0);
     }
