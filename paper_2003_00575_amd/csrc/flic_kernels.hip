@@ -220,8 +220,6 @@ void k_tile_label(BatchRef ref) {
     static_assert(kTilePx <= kNoRoot, "tile indices fit 16 bits");
     __shared__ float rs[LR * RS];
     __shared__ int par[kTilePx];
-    __shared__ float c2h[N][TW];
-    __shared__ float c2v[N][LR];              // [k-1][x + N]: rows x and x + k
 
     ScanDesc d;
     int tile;
@@ -233,15 +231,21 @@ void k_tile_label(BatchRef ref) {
     const float t2 = d.t2;
     const int lane = threadIdx.x & 63, wave = wave_id();
     const float nan = __builtin_nanf("");
+    const int ch = wave % CH, R0 = (wave / CH) * kRowsPerWave;
+    const int c = ch * 64 + lane;
 
-    for (int i = threadIdx.x; i < N * TW; i += kLabelThreads) {
-        const int k = i / TW, c = i % TW;
-        c2h[k][c] = (c < tw) ? 2.0f * d.cos_h[(size_t)k * W + c0 + c] : 0.0f;
-    }
-    for (int i = threadIdx.x; i < N * LR; i += kLabelThreads) {
-        const int k = i / LR, x = i % LR - N;
-        c2v[k][x + N] = (x >= 0 && x < th && r0 + x + k + 1 < H)
-                            ? 2.0f * d.cos_v[(size_t)k * H + r0 + x] : 0.0f;
+    // The table values this wavefront needs, loaded into registers together
+    // with the ranges (unconditional loads from clamped, in-bounds addresses;
+    // masked when used): cos_h of this lane's column, and lane l holds cos_v
+    // of strip row x = R0 - N + l (rows x and x + k).
+    static_assert(kRowsPerWave + kMaxSkip <= 64, "one lane per strip row");
+    const gptr<const float> gcos_h = global(d.cos_h), gcos_v = global(d.cos_v);
+    const int xl = R0 - N + lane;
+    float cosh_l[N], cosv_l[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        cosh_l[k] = gcos_h[(unsigned)(k * W + c0 + min(c, tw - 1))];
+        cosv_l[k] = gcos_v[(unsigned)(k * H + r0 + min(max(xl, 0), th - 1))];
     }
     // tile row x lives at LDS row x + N
     const float* src = d.range + (size_t)r0 * W + c0;
@@ -295,13 +299,20 @@ void k_tile_label(BatchRef ref) {
         slot_v[u] = (it < n_slots && border_slot<TW, N>(it, tw, th, rr, cc)) ? rs[(rr + N) * RS + cc] : nan;
     }
 
-    const int ch = wave % CH, R0 = (wave / CH) * kRowsPerWave;
-    const int c = ch * 64 + lane;
     const uint64_t le = lanes_le(lane);
     const float* at = rs + N * RS + c;                    // at[x * RS + k]: tile row x, column c + k
-    float c2hk[N];
+    // 2*cos per lane: c2hk[k-1] for this column and k columns right, c2vl[k-1]
+    // for strip row R0 - N + lane and k rows down (0 outside the tile / table)
+    float c2hk[N], c2vl[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) c2hk[k] = c2h[k][c];
+    for (int k = 0; k < N; ++k) {
+        c2hk[k] = c < tw ? 2.0f * cosh_l[k] : 0.0f;
+        c2vl[k] = (xl >= 0 && xl < th && r0 + xl + k + 1 < H) ? 2.0f * cosv_l[k] : 0.0f;
+    }
+    // the (wave-uniform) 2*cos between strip rows R0 - N + l and R0 - N + l + k
+    auto c2v = [&](int k, int l) __attribute__((always_inline)) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c2vl[k - 1]), l));
+    };
 
     // Window of the N rows above the current one: value, square, direct
     // horizontal ballot (h1) and direct vertical ballot to the row above it
@@ -319,7 +330,7 @@ void k_tile_label(BatchRef ref) {
         wv1[j] = 0;
         if (j + 1 < N) {                                  // row x - 1 >= -N
             const float up = at[(x - 1) * RS];
-            wv1[j] = ballot(connected_sq(up, up * up, wv[j], ws[j], c2v[0][x - 1 + N], t2));
+            wv1[j] = ballot(connected_sq(up, up * up, wv[j], ws[j], c2v(1, N - 2 - j), t2));
         }
     }
 
@@ -341,7 +352,7 @@ void k_tile_label(BatchRef ref) {
         // direct edges (k = 1)
         const float b1 = at[r * RS + 1];
         const uint64_t h1 = ballot(connected_sq(a, sa, b1, b1 * b1, c2hk[0], t2));
-        const uint64_t v1 = ballot(connected_sq(wv[0], ws[0], a, sa, c2v[0][r - 1 + N], t2));
+        const uint64_t v1 = ballot(connected_sq(wv[0], ws[0], a, sa, c2v(1, j - 1 + N), t2));
         const uint64_t vmask = ballot(a == a);
         const uint64_t link = v1 & ~((v1 & h1 & wh1[0]) << 1);   // pruned direct vertical edges
         if (CH > 1 && ch + 1 < CH && lane == 63 && (h1 >> 63)) t |= 1u;
@@ -383,7 +394,7 @@ void k_tile_label(BatchRef ref) {
             uint64_t chain = v1;
 #pragma unroll
             for (int k = 2; k <= N; ++k) {
-                const uint64_t vk = ballot(connected_sq(wv[k - 1], ws[k - 1], a, sa, c2v[k - 1][r - k + N], t2));
+                const uint64_t vk = ballot(connected_sq(wv[k - 1], ws[k - 1], a, sa, c2v(k, j - k + N), t2));
                 chain &= wv1[k - 2];
                 const uint64_t vneed = vk & ~((vk & h1 & wh1[k - 1]) << 1) & ~chain;
                 if (lane_bit(vneed)) t |= 1u << k;
