@@ -40,6 +40,8 @@ def lib() -> ctypes.CDLL:
         L.flic_oracle_cluster.restype = ctypes.c_int32
         L.flic_oracle_cluster.argtypes = [fp, ctypes.c_int32, ctypes.c_int32, fp, fp,
                                           ctypes.c_float, ctypes.c_int32, ip]
+        L.flic_oracle_filter_small.restype = ctypes.c_int32
+        L.flic_oracle_filter_small.argtypes = [ip, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ip]
         L.flic_oracle_dist2.restype = ctypes.c_float
         L.flic_oracle_dist2.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
         _lib = L
@@ -71,14 +73,30 @@ def cluster_status(range_img: np.ndarray, cos_v: np.ndarray, cos_h: np.ndarray,
     return st, out[: H * W].reshape(H, W) if H * W > 0 else out[:0]
 
 
-def cluster(range_img: np.ndarray, cos_v: np.ndarray, cos_h: np.ndarray,
-            threshold: float, skip_depth: int) -> np.ndarray:
-    """Labels int32 [H, W]: minimum linear index of each component, -1 if missing."""
-    st, out = cluster_status(range_img, cos_v, cos_h, threshold, skip_depth)
+def filter_small(labels: np.ndarray, min_points: int) -> np.ndarray:
+    """Section III.B.1 size threshold: labels of components with fewer than
+    min_points pixels become -1."""
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    H, W = lab.shape
+    out = np.empty_like(lab)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    st = lib().flic_oracle_filter_small(lab.ctypes.data_as(ip), H, W, int(min_points),
+                                        out.ctypes.data_as(ip))
     if st != 0:
-        raise ValueError(f"flic_oracle_cluster failed with status {st}")
+        raise ValueError(f"flic_oracle_filter_small failed with status {st}")
     return out
 
 
-def cluster_scan(scan) -> np.ndarray:
-    return cluster(scan.range_img, scan.cos_v, scan.cos_h, scan.threshold, scan.skip_depth)
+def cluster(range_img: np.ndarray, cos_v: np.ndarray, cos_h: np.ndarray,
+            threshold: float, skip_depth: int, min_points: int = 0) -> np.ndarray:
+    """Labels int32 [H, W]: minimum linear index of each component, -1 if
+    missing or (min_points > 0) in a component of fewer than min_points pixels."""
+    st, out = cluster_status(range_img, cos_v, cos_h, threshold, skip_depth)
+    if st != 0:
+        raise ValueError(f"flic_oracle_cluster failed with status {st}")
+    return filter_small(out, min_points) if min_points > 0 else out
+
+
+def cluster_scan(scan, min_points: int = 0) -> np.ndarray:
+    return cluster(scan.range_img, scan.cos_v, scan.cos_h, scan.threshold, scan.skip_depth,
+                   min_points)

@@ -10,6 +10,8 @@
  * of Section III.B.2), then label each connected component by breadth-first
  * search seeded in raster order, so the seed -- the first pixel of its
  * component in raster order -- is the component's minimum linear index.
+ * The cluster-size threshold of Section III.B.1 is a separate step on those
+ * labels: count the pixels of every label, then drop the small labels.
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math (x86-64 SSE float math:
  * every float operation is one IEEE binary32 rounding).
@@ -137,5 +139,29 @@ int32_t flic_oracle_cluster(const float* range, int32_t H, int32_t W,
     }
     memcpy(labels_out, lab, P * sizeof(int32_t));
     free(off); free(adj); free(queue); free(lab);
+    return 0;
+}
+
+/* Section III.B.1: a labelled cluster with fewer than min_points measurements
+ * is not a cluster candidate; its pixels become -1 like missing ones.  Plain
+ * definition: one histogram pass over the canonical labels, one filter pass.
+ * min_points == 0 leaves the labels as they are. */
+int32_t flic_oracle_filter_small(const int32_t* labels, int32_t H, int32_t W,
+                                 int32_t min_points, int32_t* labels_out) {
+    if (!labels || !labels_out) return -1;
+    if (H < 1 || W < 1 || min_points < 0) return -1;
+    if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX) return -1;
+    const size_t P = (size_t)H * (size_t)W;
+    for (size_t i = 0; i < P; ++i)
+        if (labels[i] < -1 || labels[i] >= (int64_t)P) return -1;
+    int64_t* count = (int64_t*)calloc(P, sizeof(int64_t));
+    if (!count) return -2;
+    for (size_t i = 0; i < P; ++i)
+        if (labels[i] >= 0) count[labels[i]] += 1;
+    for (size_t i = 0; i < P; ++i) {
+        const int32_t l = labels[i];
+        labels_out[i] = (l >= 0 && count[l] >= min_points) ? l : -1;
+    }
+    free(count);
     return 0;
 }

@@ -19,6 +19,8 @@
  *     of Section III.B.2, taken densely).
  *   - Output: each measurement gets the smallest linear index r*W + c of its
  *     connected component; missing pixels get -1.
+ *   - Optional cluster-size threshold (Section III.B.1, 100 points in the
+ *     paper): components with fewer measurements are relabelled -1.
  */
 #ifndef FLIC_ORACLE_H
 #define FLIC_ORACLE_H
@@ -46,6 +48,14 @@ int32_t flic_oracle_cluster(const float* range, int32_t H, int32_t W,
                             const float* cos_v, const float* cos_h,
                             float threshold, int32_t skip_depth,
                             int32_t* labels_out);
+
+/* Cluster-size threshold (Section III.B.1): every pixel whose label occurs
+ * fewer than min_points times in `labels` becomes -1; others keep their
+ * label.  labels is host [H][W] int32 with entries -1 or in [0, H*W);
+ * labels_out may equal labels.  min_points >= 0 (0 and 1 keep every label).
+ * Returns 0, -1 for invalid arguments, -2 when memory runs out.            */
+int32_t flic_oracle_filter_small(const int32_t* labels, int32_t H, int32_t W,
+                                 int32_t min_points, int32_t* labels_out);
 
 #ifdef __cplusplus
 }
