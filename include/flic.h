@@ -18,6 +18,9 @@
  *      canonical labels: every measurement gets the smallest linear index
  *      r*W + c of its component; missing pixels get -1.  The result is unique,
  *      so every entry point returns the same bits for the same input.
+ *   4. Optional cluster-size threshold (Section III.B.1, 100 points in the
+ *      paper): with min_points > 0, every pixel of a component with fewer
+ *      than min_points measurements gets -1 as well.
  *
  * Conventions for every entry point:
  *   - Device pointers are HIP device addresses on the context's device.
@@ -64,7 +67,12 @@ typedef struct {
  *   range_img  [H][W] float32 metres, row-major (row = channel, col = azimuth)
  *   H >= 1, W > 2*skip_depth, H*W <= INT32_MAX
  *   threshold  metres, finite, >= 0      skip_depth  N, 1..FLIC_MAX_SKIP
- *   labels_out [H][W] int32, scan-local linear indices                    */
+ *   labels_out [H][W] int32, scan-local linear indices
+ *   min_points cluster-size threshold of Section III.B.1: 0 = none; > 0 =
+ *              components with fewer measurements are labelled -1 (1 keeps
+ *              every component but still runs the counting kernels);
+ *              < 0 is FLIC_EINVAL.  The library then also keeps an
+ *              [H][W] int32 count array in its scratch.                   */
 typedef struct {
     const float* range_img;
     int32_t H;
@@ -73,6 +81,7 @@ typedef struct {
     float threshold;
     int32_t skip_depth;
     int32_t* labels_out;
+    int32_t min_points;
 } flic_scan;
 
 typedef struct flic_ctx flic_ctx;
@@ -113,15 +122,17 @@ flic_status flic_cluster_batched(flic_ctx* ctx, const flic_scan* scans,
                                  int32_t n, void* hip_stream);
 
 /* Build a reusable plan for batches shaped like `scans` (same n, and per
- * entry the same H, W and skip_depth): descriptors are laid out once on the
+ * entry the same H, W, skip_depth and min_points > 0 or not): descriptors are laid out once on the
  * device, tile shapes come from the autotune table, and the launch sequence
  * is captured in a hipGraph.                                               */
 flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n,
                              flic_plan** out);
 
 /* Launch a plan on `hip_stream` for `scans`, which must match the plan's
- * shapes entry by entry (pointers and thresholds may differ: changed
- * descriptors are uploaded before the graph launch).  FLIC_EINVAL on a
+ * shapes entry by entry: the same H, W, skip_depth, and min_points zero
+ * where the plan's is zero, positive where it is positive.  Pointers,
+ * thresholds and positive min_points values may differ: changed
+ * descriptors are uploaded before the graph launch.  FLIC_EINVAL on a
  * shape mismatch.                                                          */
 flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
                              void* hip_stream);

@@ -19,27 +19,46 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # binary32 operations (no fused multiply-add), bit-identical to the CPU.
 # -packed-fp32-ops off: no v_pk_*_f32 instructions are generated.
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),
 ]
+TILE_WIDTHS = (64, 128, 256)
+OBJ_DIR = os.path.join(HERE, "_build")
 
 
 def build(verbose: bool = False) -> str:
+    """Compile the kernels once per tile width and the host API, in
+    parallel, then link libflic.so."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    cmds = []
+    for tw in TILE_WIDTHS:
+        obj = os.path.join(OBJ_DIR, f"flic_kernels_w{tw}.o")
+        cmds.append((obj, [HIPCC, *FLAGS, f"-DFLIC_TILE_W={tw}", "-c", "-o", obj, SOURCES[0]]))
+    api_obj = os.path.join(OBJ_DIR, "flic_api.o")
+    cmds.append((api_obj, [HIPCC, *FLAGS, "-c", "-o", api_obj, SOURCES[1]]))
+    procs = []
+    for obj, cmd in cmds:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((obj, subprocess.Popen(cmd)))
+    failed = [obj for obj, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, f"hipcc ({', '.join(os.path.basename(f) for f in failed)})")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in cmds]]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 
 
 def device_asm(out_path: str) -> str:
     """Write the gfx950 assembly of the kernels (for instruction checks)."""
-    cmd = [HIPCC, *[f for f in FLAGS if f not in ("-shared", "-fPIC")], "-S", "--cuda-device-only",
+    cmd = [HIPCC, *[f for f in FLAGS if f != "-fPIC"], "-S", "--cuda-device-only",
            "-o", out_path, SOURCES[0]]
     subprocess.check_call(cmd)
     return out_path

@@ -77,6 +77,7 @@ flic_status check_scans(const flic_scan* scans, int32_t n) {
         flic_status st = check_scan(s.range_img, s.H, s.W, &s.tables, s.threshold, s.skip_depth,
                                     s.labels_out, i);
         if (st != FLIC_OK) return st;
+        if (s.min_points < 0) return fail(FLIC_EINVAL, "scan %d: min_points %d < 0", i, s.min_points);
     }
     // no scan may write into another scan's buffers
     for (int32_t i = 0; i < n; ++i) {
@@ -90,6 +91,17 @@ flic_status check_scans(const flic_scan* scans, int32_t n) {
         }
     }
     return FLIC_OK;
+}
+
+hipError_t launch_cluster(const flic::BatchRef& ref, int tile_w, int skip, bool sized, int n_tiles,
+                          int n_scans, hipStream_t stream, hipEvent_t* events = nullptr) {
+    if (n_tiles <= 0 || n_scans <= 0) return hipSuccess;
+    switch (tile_w) {
+        case 64: return flic::launch_cluster_tw<64>(ref, skip, sized, n_tiles, n_scans, stream, events);
+        case 128: return flic::launch_cluster_tw<128>(ref, skip, sized, n_tiles, n_scans, stream, events);
+        case 256: return flic::launch_cluster_tw<256>(ref, skip, sized, n_tiles, n_scans, stream, events);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t set_device(int dev) {
@@ -135,9 +147,10 @@ struct flic_plan {
     flic_ctx* ctx = nullptr;
     int32_t n = 0;
     std::vector<flic_scan> shapes;     // shapes as planned
-    struct Group {                     // scans sharing one tile width and skip depth
+    struct Group {                     // scans sharing tile width, skip depth and sizing
         int tile_w;
         int skip;
+        bool sized;
         int n_tiles;
         size_t desc_off;               // byte offset of ScanDesc[members] in the blob
         std::vector<int> members;      // scan indices
@@ -168,6 +181,8 @@ int choose_tile_w(const flic_ctx* ctx, int32_t H, int32_t W, int32_t N) {
     return 64;
 }
 
+bool sized(const flic_scan& s) { return s.min_points > 0; }
+
 ScanDesc make_desc(const flic_scan& s, int tile_w, int32_t tile_begin, char* scratch) {
     ScanDesc d{};
     d.range = s.range_img;
@@ -184,10 +199,12 @@ ScanDesc make_desc(const flic_scan& s, int tile_w, int32_t tile_begin, char* scr
     d.tiles_y = (s.H + d.tile_h - 1) / d.tile_h;
     d.chunks_per_row = (s.W + 63) / 64;
     d.tile_begin = tile_begin;
-    const flic::ScratchLayout S = flic::scratch_layout(s.H, s.W, s.skip_depth, tile_w);
+    d.min_points = s.min_points;
+    const flic::ScratchLayout S = flic::scratch_layout(s.H, s.W, s.skip_depth, tile_w, sized(s));
     d.masks = reinterpret_cast<ulonglong2*>(scratch + S.masks);
     d.runs = reinterpret_cast<uint16_t*>(scratch + S.runs);
     d.parent = reinterpret_cast<int32_t*>(scratch + S.parent);
+    d.counts = sized(s) ? reinterpret_cast<int32_t*>(scratch + S.counts) : nullptr;
     d.bcol_v = reinterpret_cast<float*>(scratch + S.bcol_v);
     d.bcol_r = reinterpret_cast<int32_t*>(scratch + S.bcol_r);
     d.brow_v = reinterpret_cast<float*>(scratch + S.brow_v);
@@ -199,17 +216,21 @@ size_t scratch_bytes(const flic_ctx* ctx, const flic_scan* scans, int32_t n) {
     size_t total = 0;
     for (int32_t i = 0; i < n; ++i)
         total += flic::scratch_layout(scans[i].H, scans[i].W, scans[i].skip_depth,
-                                      choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth)).total;
+                                      choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth),
+                                      sized(scans[i])).total;
     return total;
 }
 
-// Descriptors + block maps for a batch, grouped by (tile width, skip depth),
+// Descriptors + block maps for a batch, grouped by (tile width, skip depth,
+// size threshold or not),
 // as one byte image: per group ScanDesc[members] then int32 block_scan[tiles].
 // Scans take consecutive scratch regions starting at `scratch`.
 struct Layout {
     std::vector<char> blob;
     struct G {
-        int tile_w, skip, n_tiles;
+        int tile_w, skip;
+        bool sized;
+        int n_tiles;
         size_t desc_off, map_off;
         std::vector<int> members;
     };
@@ -224,13 +245,16 @@ void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, char* 
     for (int32_t i = 0; i < n; ++i) {
         base[i] = scratch + off;
         off += flic::scratch_layout(scans[i].H, scans[i].W, scans[i].skip_depth,
-                                    choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth)).total;
+                                    choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth),
+                                    sized(scans[i])).total;
     }
     const int widths[3] = {64, 128, 256};
-    for (int gi = 0; gi < 3 * FLIC_MAX_SKIP; ++gi) {
-        Layout::G g{widths[gi / FLIC_MAX_SKIP], 1 + gi % FLIC_MAX_SKIP, 0, 0, 0, {}};
+    for (int gi = 0; gi < 2 * 3 * FLIC_MAX_SKIP; ++gi) {
+        const int gw = gi % (3 * FLIC_MAX_SKIP);
+        Layout::G g{widths[gw / FLIC_MAX_SKIP], 1 + gw % FLIC_MAX_SKIP, gi >= 3 * FLIC_MAX_SKIP, 0, 0, 0, {}};
         for (int32_t i = 0; i < n; ++i)
-            if (choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth) == g.tile_w && scans[i].skip_depth == g.skip)
+            if (choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth) == g.tile_w &&
+                scans[i].skip_depth == g.skip && sized(scans[i]) == g.sized)
                 g.members.push_back(i);
         if (g.members.empty()) continue;
         std::vector<ScanDesc> descs;
@@ -283,8 +307,8 @@ flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t st
         hipError_t e;
         hipEvent_t* ev = timing_events(timing_ctx, &e);
         HIP_TRY(e);
-        HIP_TRY(flic::launch_cluster(ref, g.tile_w, g.skip, g.n_tiles, (int)g.members.size(),
-                                     stream, ev));
+        HIP_TRY(launch_cluster(ref, g.tile_w, g.skip, g.sized, g.n_tiles, (int)g.members.size(),
+                               stream, ev));
     }
     return FLIC_OK;
 }
@@ -467,19 +491,19 @@ flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img, int32_t H,
     if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
     flic_status st = check_scan(range_img, H, W, alpha_tables, threshold, skip_depth, labels_out, 0);
     if (st != FLIC_OK) return st;
-    const flic_scan s{range_img, H, W, *alpha_tables, threshold, skip_depth, labels_out};
+    const flic_scan s{range_img, H, W, *alpha_tables, threshold, skip_depth, labels_out, 0};
     const int tw = choose_tile_w(ctx, H, W, skip_depth);
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(set_device(ctx->device));
     flic_ctx::Slot* slot = nullptr;
-    st = acquire_slot(ctx, 0, flic::scratch_layout(H, W, skip_depth, tw).total, &slot);
+    st = acquire_slot(ctx, 0, flic::scratch_layout(H, W, skip_depth, tw, false).total, &slot);
     if (st != FLIC_OK) return st;
     flic::BatchRef ref{};
     ref.one = make_desc(s, tw, 0, static_cast<char*>(slot->scratch));
     hipError_t e;
     hipEvent_t* ev = timing_events(ctx, &e);
     HIP_TRY(e);
-    HIP_TRY(flic::launch_cluster(ref, tw, skip_depth, ref.one.tiles_x * ref.one.tiles_y, 1, stream, ev));
+    HIP_TRY(launch_cluster(ref, tw, skip_depth, false, ref.one.tiles_x * ref.one.tiles_y, 1, stream, ev));
     HIP_TRY(hipEventRecord(slot->done, stream));
     slot->pending = true;
     return FLIC_OK;
@@ -562,7 +586,8 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, f
     ctx->used += scratch;
     build_layout(ctx, scans, n, static_cast<char*>(p->scratch), L);
     p->blob_bytes = L.blob.size();
-    for (const auto& g : L.groups) p->groups.push_back({g.tile_w, g.skip, g.n_tiles, g.desc_off, g.members});
+    for (const auto& g : L.groups)
+        p->groups.push_back({g.tile_w, g.skip, g.sized, g.n_tiles, g.desc_off, g.members});
     if (hipMalloc(&p->dev_mem, p->blob_bytes) != hipSuccess) {
         p->dev_mem = nullptr;
         return cleanup(fail(FLIC_ENOMEM, "hipMalloc(%zu) failed", p->blob_bytes));
@@ -605,10 +630,13 @@ flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
         const flic_scan& b = plan->shapes[i];
         if (a.H != b.H || a.W != b.W || a.skip_depth != b.skip_depth)
             return fail(FLIC_EINVAL, "scan %d shape differs from the plan", i);
+        if (sized(a) != sized(b))
+            return fail(FLIC_EINVAL, "scan %d: min_points %s 0 in the plan but %d now", i,
+                        sized(b) ? ">" : "==", a.min_points);
     }
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(set_device(plan->ctx->device));
-    // Refresh descriptors whose pointers or threshold changed (scratch stays
+    // Refresh descriptors whose pointers, threshold or min_points changed (scratch stays
     // the plan's own).  The pinned staging copy is rewritten only after the
     // previous launch, and with it the previous upload, has completed.
     std::vector<std::pair<size_t, ScanDesc>> changed;
@@ -624,6 +652,7 @@ flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
             nd.cos_v = s.tables.cos_v;
             nd.cos_h = s.tables.cos_h;
             nd.t2 = s.threshold * s.threshold;
+            nd.min_points = s.min_points;
             if (memcmp(&nd, &old, sizeof nd) != 0) changed.push_back({off, nd});
         }
     }

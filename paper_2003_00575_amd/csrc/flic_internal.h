@@ -26,9 +26,14 @@ constexpr int kRunHead = 16;
 //   runs    [chunks_per_row][H][kRunHead] uint16: tile-local root of the
 //           chunk's k-th run (k < kRunHead); runs k >= kRunHead keep theirs
 //           at position k of the chunk's label segment.
-//   parent  [H*W] int32, used only at tile-root positions: the global
-//           union-find of the tile components (written for every tile root
-//           by pass 1, joined by pass 2, read by pass 3).
+//   parent  [H*W] int32, used only at tile-root positions, and only by
+//           pass 2 when the scan's border roots overflow its LDS tables:
+//           the union-find of the tile components in global memory.
+//   counts  [H*W] int32 (scans with a size threshold only), used only at
+//           tile-root positions: pass 1 stores each tile component's pixel
+//           count there, pass 2 adds every non-final root's count to its
+//           final root, pass 3 compares the final root's count with
+//           min_points.
 //   bcol_v / bcol_r  [tiles][2][N][tile_h]: range and provisional root of the
 //           first (side 0) and last (side 1) N columns of each tile.
 //   brow_v / brow_r  [tiles][2][N][tile_w]: the same for the first and last N
@@ -44,6 +49,7 @@ struct ScanDesc {
     ulonglong2* masks;
     uint16_t* runs;
     int32_t* parent;
+    int32_t* counts;        // null without a size threshold
     float* bcol_v;
     int32_t* bcol_r;
     float* brow_v;
@@ -55,6 +61,7 @@ struct ScanDesc {
     int32_t tiles_x, tiles_y;
     int32_t chunks_per_row; // ceil(W / 64)
     int32_t tile_begin;     // first global tile id of this scan in its batch
+    int32_t min_points;     // size threshold (0: none; the kernels read it only when counting)
 };
 
 // Where a launch finds its scans: a device table plus a block -> scan map,
@@ -70,12 +77,13 @@ inline int tile_h_for(int tile_w) { return kTilePx / tile_w; }
 // Scratch bytes one scan needs, and the sub-buffer offsets (each 256-byte
 // aligned) relative to the scan's scratch base.
 struct ScratchLayout {
-    size_t masks, runs, parent, bcol_v, bcol_r, brow_v, brow_r, total;
+    size_t masks, runs, parent, counts, bcol_v, bcol_r, brow_v, brow_r, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline ScratchLayout scratch_layout(int H, int W, int N, int tile_w) {
+// A scan with a size threshold (sized) also has a count array.
+inline ScratchLayout scratch_layout(int H, int W, int N, int tile_w, bool sized) {
     const int tile_h = tile_h_for(tile_w);
     const size_t tiles = (size_t)((W + tile_w - 1) / tile_w) * ((H + tile_h - 1) / tile_h);
     const bool rows = H > tile_h;
@@ -84,6 +92,7 @@ inline ScratchLayout scratch_layout(int H, int W, int N, int tile_w) {
     L.masks = o;  o = align256(o + (size_t)H * ((W + 63) / 64) * 16);
     L.runs = o;   o = align256(o + (size_t)H * ((W + 63) / 64) * kRunHead * 2);
     L.parent = o; o = align256(o + (size_t)H * W * 4);
+    L.counts = o; o = align256(o + (sized ? (size_t)H * W * 4 : 0));
     L.bcol_v = o; o = align256(o + tiles * 2 * N * tile_h * 4);
     L.bcol_r = o; o = align256(o + tiles * 2 * N * tile_h * 4);
     L.brow_v = o; o = align256(o + (rows ? tiles * 2 * N * tile_w * 4 : 0));
@@ -95,11 +104,14 @@ inline ScratchLayout scratch_layout(int H, int W, int N, int tile_w) {
 constexpr int kPasses = 3;
 
 // Enqueue the three passes (tile labelling, scan merge, relabel) for
-// `n_scans` scans with `n_tiles` tiles in total, of tile width `tile_w`
-// (64, 128 or 256) and skip depth `skip` (1..kMaxSkip).  When `events` is
-// non-null, events[0] is recorded before the first pass and events[i + 1]
-// after pass i.
-hipError_t launch_cluster(const BatchRef& ref, int tile_w, int skip, int n_tiles, int n_scans,
-                          hipStream_t stream, hipEvent_t* events = nullptr);
+// `n_scans` scans with `n_tiles` tiles in total, of tile width TW (64, 128
+// or 256) and skip depth `skip` (1..kMaxSkip); `sized` selects the kernels
+// that also count component sizes and apply each scan's min_points.  When
+// `events` is non-null, events[0] is recorded before the first pass and
+// events[i + 1] after pass i.
+template <int TW>
+hipError_t launch_cluster_tw(const BatchRef& ref, int skip, bool sized, int n_tiles, int n_scans,
+                             hipStream_t stream, hipEvent_t* events);
+
 
 }  // namespace flic

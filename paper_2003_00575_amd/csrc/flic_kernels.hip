@@ -209,7 +209,10 @@ __device__ __forceinline__ bool border_slot(int it, int tw, int th, int& rr, int
     return cc >= 0 && cc < tw && rr >= 0 && rr < th;
 }
 
-template <int TW, int N>
+// SIZE (scans with a cluster-size threshold): the pixels of every tile
+// component are also counted, in LDS, and the count is stored at the
+// component's tile root in the scan's count array.
+template <int TW, int N, bool SIZE>
 __global__ __launch_bounds__(kLabelThreads) __attribute__((amdgpu_waves_per_eu(N <= 3 ? 8 : 4)))
 void k_tile_label(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
@@ -492,6 +495,12 @@ void k_tile_label(BatchRef ref) {
             if (root != x)
                 __hip_atomic_fetch_min(&par[x], root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        // SIZE: the queues become the per-root pixel counts (indexed by
+        // tile-local root), each wavefront clearing its own slice
+        if constexpr (SIZE) {
+#pragma unroll
+            for (int i = 0; i < kRowsPerWave; ++i) queue[i * 64 + lane] = 0;
+        }
     }
     __syncthreads();
 
@@ -515,6 +524,7 @@ void k_tile_label(BatchRef ref) {
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) node[j] = lds_load(&par[node[j]]);
     // run roots; the masks of all rows in one store (words, built above)
+    [[maybe_unused]] unsigned own_root = 0;              // SIZE: rows where this lane is a tile root
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
         const uint64_t starts = row_mask(words, 4 * j);
@@ -526,6 +536,15 @@ void k_tile_label(BatchRef ref) {
                 (runs + (mrow + j) * kRunHead)[k] = (uint16_t)root;
             else
                 (labels + (lbase + j * W))[k] = root;
+            if constexpr (SIZE) {
+                // the run ends before the next run head or missing pixel of
+                // the chunk (runs never cross a chunk border)
+                const uint64_t ends = (starts | ~row_mask(words, 4 * j + 2)) & ~le;
+                const int len = (ends ? __builtin_ctzll(ends) : 64) - lane;
+                __hip_atomic_fetch_add(reinterpret_cast<int*>(rs) + root, len, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                if ((int)root == (R0 + j) * TW + c) own_root |= 1u << j;
+            }
         }
     }
     if (lane < 4 * rows) (mask_words + 4 * mrow)[lane] = words;
@@ -558,6 +577,17 @@ void k_tile_label(BatchRef ref) {
             brow_v[it - kColItems] = slot_v[u];
             brow_r[it - kColItems] = groot;
         }
+    }
+
+    // SIZE: every tile root's pixel count (a tile root is the run head at
+    // the component's smallest tile index, so exactly one lane holds it)
+    if constexpr (SIZE) {
+        __syncthreads();
+        const gptr<int> counts = global(d.counts);
+#pragma unroll
+        for (int j = 0; j < kRowsPerWave; ++j)
+            if ((own_root >> j) & 1u)
+                (counts + lbase)[j * W + lane] = reinterpret_cast<const int*>(rs)[(R0 + j) * TW + c];
     }
 }
 
@@ -843,7 +873,10 @@ __device__ __forceinline__ void set_slot_final(const ScanDesc& d, int i, int n_c
         reinterpret_cast<int*>(d.brow_v)[i - n_col] = f;
 }
 
-template <int TW, int N>
+// SIZE: after the joins, the pixel count of every border root that is not
+// its component's final root is added to the final root's count, so the
+// count array holds every component's size at its final root.
+template <int TW, int N, bool SIZE>
 __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
     __shared__ int keys[kNodeCap];             // node -> global root (kNoKey: free)
@@ -905,6 +938,16 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
                 if (r[u] >= 0)
                     set_slot_final(d, i0 + u * kMergeThreads, n_col, keys[node_find(npar, node_of(keys, r[u]))]);
         }
+        if constexpr (SIZE) {
+            // one node per border root; a non-final root's count is read
+            // only here (only final roots receive additions)
+            for (int i = threadIdx.x; i < kNodeCap; i += kMergeThreads) {
+                const int k = keys[i];
+                if (k == kNoKey) continue;
+                const int f = keys[node_find(npar, i)];
+                if (f != k) atomicAdd(&d.counts[f], d.counts[k]);
+            }
+        }
         return;
     }
 
@@ -943,7 +986,16 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
     const bool walk = overflow != 0;
     for (int i = threadIdx.x; i < n_slots; i += kMergeThreads) {
         const int r = slot_root(d, i, n_col);
-        if (r >= 0) set_slot_final(d, i, n_col, walk ? wg_find(par, r) : wg_load(&par[r]));
+        if (r < 0) continue;
+        const int f = walk ? wg_find(par, r) : wg_load(&par[r]);
+        set_slot_final(d, i, n_col, f);
+        if constexpr (SIZE) {
+            // a root has many slots: the first to take its count moves it
+            if (f != r) {
+                const int v = atomicExch(&d.counts[r], 0);
+                if (v != 0) atomicAdd(&d.counts[f], v);
+            }
+        }
     }
 }
 
@@ -966,7 +1018,10 @@ __device__ __forceinline__ uint64_t lane_word(uint64_t v, int j) {
 constexpr int kRelabelRows = 16;
 constexpr int kRelabelThreads = kTilePx / kRelabelRows;
 
-template <int TW>
+// SIZE: a label whose component has fewer than min_points pixels (the count
+// at its final root) becomes -1; the 16 rows' counts are gathered together
+// before the stores.
+template <int TW, bool SIZE>
 __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
     constexpr int CH = TW / 64;
@@ -1031,6 +1086,7 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     // ... then, row by row: every pixel's run root (from the run array, or
     // for runs beyond the first kRunHead of a chunk from its label segment)
     // and its final root, one store per pixel
+    [[maybe_unused]] int outs[kRelabelRows];
 #pragma unroll
     for (int j = 0; j < kRelabelRows; ++j) {
         const gptr<int> row = global(d.labels) + ((size_t)(r0 + R0 + j) * W + c0 + ch * 64);   // scalar base
@@ -1050,50 +1106,73 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
         local &= kTilePx - 1;
         const int f = fin[local];
         const int out = lane_bit(valid) ? (f >= 0 ? f : (int)(base + (local / TW) * W + (local % TW))) : -1;
-        if (j < rows && col_in) row[lane] = out;
+        if constexpr (SIZE)
+            outs[j] = out;
+        else if (j < rows && col_in)
+            row[lane] = out;
+    }
+    if constexpr (SIZE) {
+        const gptr<const int> counts = global(static_cast<const int*>(d.counts));
+        const int m = d.min_points;
+        int n[kRelabelRows];
+#pragma unroll
+        for (int j = 0; j < kRelabelRows; ++j) n[j] = outs[j] >= 0 ? counts[(unsigned)outs[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < kRelabelRows; ++j) {
+            const gptr<int> row = global(d.labels) + ((size_t)(r0 + R0 + j) * W + c0 + ch * 64);
+            if (j < rows && col_in) row[lane] = n[j] >= m ? outs[j] : -1;
+        }
     }
 }
 
-template <int TW, int N>
+template <int TW, int N, bool SIZE>
 hipError_t launch_twn(const BatchRef& ref, int n_tiles, int n_scans, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tile_label<TW, N>), dim3(n_tiles), dim3(kLabelThreads), 0, stream, ref);
+    hipLaunchKernelGGL((k_tile_label<TW, N, SIZE>), dim3(n_tiles), dim3(kLabelThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan_merge<TW, N>), dim3(n_scans), dim3(kMergeThreads), 0, stream, ref);
+    hipLaunchKernelGGL((k_scan_merge<TW, N, SIZE>), dim3(n_scans), dim3(kMergeThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_relabel<TW>, dim3(n_tiles), dim3(kRelabelThreads), 0, stream, ref);
+    hipLaunchKernelGGL((k_relabel<TW, SIZE>), dim3(n_tiles), dim3(kRelabelThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
-template <int TW>
-hipError_t launch_tw(const BatchRef& ref, int skip, int n_tiles, int n_scans, hipStream_t stream,
-                     hipEvent_t* ev) {
+template <int TW, bool SIZE>
+hipError_t launch_tws(const BatchRef& ref, int skip, int n_tiles, int n_scans, hipStream_t stream,
+                      hipEvent_t* ev) {
     switch (skip) {
-        case 1: return launch_twn<TW, 1>(ref, n_tiles, n_scans, stream, ev);
-        case 2: return launch_twn<TW, 2>(ref, n_tiles, n_scans, stream, ev);
-        case 3: return launch_twn<TW, 3>(ref, n_tiles, n_scans, stream, ev);
-        case 4: return launch_twn<TW, 4>(ref, n_tiles, n_scans, stream, ev);
-        case 5: return launch_twn<TW, 5>(ref, n_tiles, n_scans, stream, ev);
-        case 6: return launch_twn<TW, 6>(ref, n_tiles, n_scans, stream, ev);
-        case 7: return launch_twn<TW, 7>(ref, n_tiles, n_scans, stream, ev);
-        case 8: return launch_twn<TW, 8>(ref, n_tiles, n_scans, stream, ev);
+        case 1: return launch_twn<TW, 1, SIZE>(ref, n_tiles, n_scans, stream, ev);
+        case 2: return launch_twn<TW, 2, SIZE>(ref, n_tiles, n_scans, stream, ev);
+        case 3: return launch_twn<TW, 3, SIZE>(ref, n_tiles, n_scans, stream, ev);
+        case 4: return launch_twn<TW, 4, SIZE>(ref, n_tiles, n_scans, stream, ev);
+        case 5: return launch_twn<TW, 5, SIZE>(ref, n_tiles, n_scans, stream, ev);
+        case 6: return launch_twn<TW, 6, SIZE>(ref, n_tiles, n_scans, stream, ev);
+        case 7: return launch_twn<TW, 7, SIZE>(ref, n_tiles, n_scans, stream, ev);
+        case 8: return launch_twn<TW, 8, SIZE>(ref, n_tiles, n_scans, stream, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_cluster(const BatchRef& ref, int tile_w, int skip, int n_tiles, int n_scans,
-                          hipStream_t stream, hipEvent_t* events) {
-    if (n_tiles <= 0 || n_scans <= 0) return hipSuccess;
-    switch (tile_w) {
-        case 64: return launch_tw<64>(ref, skip, n_tiles, n_scans, stream, events);
-        case 128: return launch_tw<128>(ref, skip, n_tiles, n_scans, stream, events);
-        case 256: return launch_tw<256>(ref, skip, n_tiles, n_scans, stream, events);
-        default: return hipErrorInvalidValue;
-    }
+// One translation unit per tile width (FLIC_TILE_W), compiled in parallel;
+// without it every width is built here.
+template <int TW>
+hipError_t launch_cluster_tw(const BatchRef& ref, int skip, bool sized, int n_tiles, int n_scans,
+                             hipStream_t stream, hipEvent_t* events) {
+    return sized ? launch_tws<TW, true>(ref, skip, n_tiles, n_scans, stream, events)
+                 : launch_tws<TW, false>(ref, skip, n_tiles, n_scans, stream, events);
 }
+
+#if !defined(FLIC_TILE_W) || FLIC_TILE_W == 64
+template hipError_t launch_cluster_tw<64>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*);
+#endif
+#if !defined(FLIC_TILE_W) || FLIC_TILE_W == 128
+template hipError_t launch_cluster_tw<128>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*);
+#endif
+#if !defined(FLIC_TILE_W) || FLIC_TILE_W == 256
+template hipError_t launch_cluster_tw<256>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*);
+#endif
 
 }  // namespace flic

@@ -34,7 +34,8 @@ class _Tables(ctypes.Structure):
 class _Scan(ctypes.Structure):
     _fields_ = [("range_img", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("tables", _Tables), ("threshold", ctypes.c_float),
-                ("skip_depth", ctypes.c_int32), ("labels_out", ctypes.c_void_p)]
+                ("skip_depth", ctypes.c_int32), ("labels_out", ctypes.c_void_p),
+                ("min_points", ctypes.c_int32)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -119,10 +120,12 @@ def cluster_async_raw(ctx: int, range_ptr: int, H: int, W: int, cos_v_ptr: int, 
 
 
 def batched_raw(ctx: int, scans: Sequence[tuple], stream: int) -> int:
-    """scans: (range_ptr, H, W, cos_v_ptr, cos_h_ptr, threshold, N, labels_ptr)."""
+    """scans: (range_ptr, H, W, cos_v_ptr, cos_h_ptr, threshold, N, labels_ptr
+    [, min_points])."""
     arr = (_Scan * max(1, len(scans)))()
-    for i, (rp, H, W, cv, ch, T, N, lp) in enumerate(scans):
-        arr[i] = _Scan(rp, H, W, _Tables(cv, ch), T, N, lp)
+    for i, sc in enumerate(scans):
+        rp, H, W, cv, ch, T, N, lp = sc[:8]
+        arr[i] = _Scan(rp, H, W, _Tables(cv, ch), T, N, lp, sc[8] if len(sc) > 8 else 0)
     return lib().flic_cluster_batched(ctx, arr, len(scans), stream)
 
 
@@ -154,13 +157,15 @@ def _check_tensor(t, dtype, shape, name):
 @dataclasses.dataclass
 class DeviceScan:
     """Device tensors of one scan: range [H, W] f32, cos_v [N, H] f32,
-    cos_h [N, W] f32, labels [H, W] int32 (output)."""
+    cos_h [N, W] f32, labels [H, W] int32 (output); min_points > 0 applies
+    the cluster-size threshold."""
     range_img: "object"
     cos_v: "object"
     cos_h: "object"
     threshold: float
     skip_depth: int
     labels: "object" = None
+    min_points: int = 0
 
     def validate(self) -> None:
         import torch
@@ -177,7 +182,8 @@ class DeviceScan:
         H, W = self.range_img.shape
         return _Scan(self.range_img.data_ptr(), H, W,
                      _Tables(self.cos_v.data_ptr(), self.cos_h.data_ptr()),
-                     float(self.threshold), int(self.skip_depth), self.labels.data_ptr())
+                     float(self.threshold), int(self.skip_depth), self.labels.data_ptr(),
+                     int(self.min_points))
 
 
 class Context:
@@ -253,6 +259,8 @@ class Context:
 
     def cluster_async(self, scan: DeviceScan, stream=None):
         scan.validate()
+        if scan.min_points:                 # the size threshold is a flic_scan field
+            return self.cluster_batched([scan], stream)[0]
         H, W = scan.range_img.shape
         t = _Tables(scan.cos_v.data_ptr(), scan.cos_h.data_ptr())
         _check(lib().flic_cluster_async(self.handle, scan.range_img.data_ptr(), H, W,
@@ -336,10 +344,11 @@ def default_context(device: Optional[int] = None) -> Context:
     return _default_ctx[device]
 
 
-def cluster(range_img, cos_v, cos_h, threshold: float, skip_depth: int, out=None, stream=None):
+def cluster(range_img, cos_v, cos_h, threshold: float, skip_depth: int, out=None, stream=None,
+            min_points: int = 0):
     """Labels int32 [H, W] of one scan, enqueued on `stream` (default: the
     current torch stream).  Inputs are device tensors."""
-    s = DeviceScan(range_img, cos_v, cos_h, threshold, skip_depth, out)
+    s = DeviceScan(range_img, cos_v, cos_h, threshold, skip_depth, out, min_points)
     return default_context(range_img.device.index).cluster_async(s, stream)
 
 
@@ -359,12 +368,12 @@ def cluster_batched(scans: Sequence[DeviceScan], stream=None):
     return default_context(scans[0].range_img.device.index).cluster_batched(scans, stream)
 
 
-def to_device(scan, device="cuda") -> DeviceScan:
+def to_device(scan, device="cuda", min_points: int = 0) -> DeviceScan:
     """Copy a host scan (synth.Scan) to device tensors."""
     import torch
     d = DeviceScan(torch.from_numpy(scan.range_img).to(device),
                    torch.from_numpy(scan.cos_v).to(device),
                    torch.from_numpy(scan.cos_h).to(device),
-                   scan.threshold, scan.skip_depth)
+                   scan.threshold, scan.skip_depth, min_points=min_points)
     d.validate()          # allocates the labels tensor
     return d

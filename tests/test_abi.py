@@ -70,3 +70,20 @@ def test_null_tables_struct_and_ctx(L):
     assert L.flic_set_tile_override(None, 64) == flic.FLIC_EINVAL
     L.flic_ctx_destroy(None)
     L.flic_plan_destroy(None)
+
+
+def test_scan_struct_layout_matches_header(tmp_path):
+    """The binding's flic_scan mirror has the header's size and field offsets."""
+    import ctypes
+    import subprocess
+    from paper_2003_00575_amd import flic
+    src = tmp_path / "layout.c"
+    fields = [f for f, _ in flic._Scan._fields_]
+    body = "\n".join(f'    printf("%zu\\n", offsetof(flic_scan, {f}));' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "flic.h"\nint main(void) {\n'
+                   f'    printf("%zu\\n", sizeof(flic_scan));\n{body}\n    return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(flic._Scan)] + [getattr(flic._Scan, f).offset for f in fields]
+    assert got == want
