@@ -8,6 +8,10 @@ batched launches of 64 scans (50.3 Mpix per step).  Each launch is a hipGraph
 plan; launches rotate over --sets disjoint copies of the inputs and outputs so
 that no launch finds its data in the 256 MB last-level cache.
 
+With --min-points M the same step also applies the cluster-size threshold of
+Section III.B.1 (components with fewer than M points labelled -1; the paper
+uses 100): the counting variants of the three kernels run instead.
+
 Prints one JSON line with whole-job throughput (Gpix/s), the dominant kernel's
 bandwidth against the HBM peak (HIP events around each kernel, same workload,
 non-graph batched launches), p50/p99 latency of the plain per-scan path on a
@@ -27,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_RECORD = os.path.join(ROOT, "profiles", "flic_passes_large_batch_64x128x2048.txt")
+PROFILE_RECORD_SIZED = os.path.join(ROOT, "profiles", "flic_passes_large_batch_64x128x2048_min100.txt")
 # vector-instruction issue peak: 256 CUs x one wave64 VALU instruction per CU
 # per cycle (4 SIMD16 units, 4 cycles each) x 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 2.4e9
@@ -84,11 +89,11 @@ def uneven_batch(ctx, flic, synth, torch, dev, stream, n=256, reps=10):
             "per_scan_scans_s": round(n / (single_ms * 1e-3), 1)}
 
 
-def dominant_traffic(name):
+def dominant_traffic(name, path):
     """HBM bytes of one launch of the named pass from the committed rocprofv3
     record, or None when there is none or the kernel source changed since."""
     from paper_2003_00575_amd import prof_summary
-    rec = prof_summary.load_record(PROFILE_RECORD)
+    rec = prof_summary.load_record(path)
     if not rec or rec.get("kernel_source_sha256") != prof_summary.kernel_source_sha256():
         return None
     return rec.get("kernels", {}).get(name)
@@ -131,7 +136,11 @@ def main() -> int:
                     help="only the timed batch and the per-kernel timing (for profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 128 MiB device copy (reference for byte counters)")
+    ap.add_argument("--min-points", type=int, default=0,
+                    help="cluster-size threshold of Section III.B.1 (0 = none; the paper uses 100)")
     args = ap.parse_args()
+    MP = max(0, args.min_points)
+    record_path = PROFILE_RECORD_SIZED if MP == 100 else (PROFILE_RECORD if MP == 0 else "")
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -163,7 +172,7 @@ def main() -> int:
               for _ in range(S)]
 
     def scans_for(s, ti):
-        return [flic.DeviceScan(ranges[s][i], cos_v[i], cos_h[i], THRESHOLDS[ti], SKIP, labels[s][ti][i])
+        return [flic.DeviceScan(ranges[s][i], cos_v[i], cos_h[i], THRESHOLDS[ti], SKIP, labels[s][ti][i], MP)
                 for i in range(N_SCANS)]
 
     from paper_2003_00575_amd import autotune
@@ -269,7 +278,7 @@ def main() -> int:
 
     # ---- latency of the plain per-scan path (64 x 2048 scan) ----------------
     c1 = synth.single_scan(1)
-    d1 = flic.to_device(c1, dev)
+    d1 = flic.to_device(c1, dev, min_points=MP)
     for _ in range(20):
         ctx.cluster_async(d1, stream)
     torch.cuda.synchronize()
@@ -295,7 +304,7 @@ def main() -> int:
     serving = None if args.no_serve else serving_excerpt(args.serve_seconds)
 
     # ---- CPU oracle on a bounded sample -------------------------------------
-    traffic = dominant_traffic(names[dom])
+    traffic = dominant_traffic(names[dom], record_path) if record_path else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -303,13 +312,14 @@ def main() -> int:
         done_px, n_calls, t = 0, 0, time.perf_counter()
         while time.perf_counter() - t < args.cpu_seconds:
             s = host[n_calls % N_SCANS]
-            oracle.cluster(s.range_img, s.cos_v, s.cos_h, THRESHOLDS[n_calls % 3], SKIP)
+            oracle.cluster(s.range_img, s.cos_v, s.cos_h, THRESHOLDS[n_calls % 3], SKIP, MP)
             done_px += H * W
             n_calls += 1
         el = time.perf_counter() - t
         cpu = {"value": round(done_px / el / 1e9, 6), "unit": "Gpix/s", "cores": 1, "kind": "oracle",
                "sample": f"{n_calls} oracle calls on the {H}x{W} scans of this batch "
-                         f"(thresholds cycling 0.3/0.5/1.0, skip 3), {el:.1f} s on one host core"}
+                         f"(thresholds cycling 0.3/0.5/1.0, skip 3"
+                         f"{f', min {MP} points' if MP else ''}), {el:.1f} s on one host core"}
 
     out = {
         "metric": "range pixels/sec (Gpix/s) batched + p50/p99 scan latency, labels bit-exact",
@@ -327,15 +337,18 @@ def main() -> int:
         "config": {"workload": f"large batch: {N_SCANS} scans x {H}x{W} f32 range images, "
                                f"thresholds 0.3/0.5/1.0 m (3 launches per step, "
                                f"{'one stream each' if args.streams > 1 else 'one stream'}), "
-                               f"skip depth {SKIP}, hipGraph plans, {S} rotating buffer sets",
+                               f"skip depth {SKIP}, "
+                               f"{f'cluster-size threshold {MP} points, ' if MP else ''}"
+                               f"hipGraph plans, {S} rotating buffer sets",
                    "global_batch": N_SCANS * len(THRESHOLDS), "pixels_per_step": px_per_step,
+                   "min_points": MP,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic.get("traffic_bytes") if traffic else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_record": None if traffic is None else {
-                         "file": os.path.relpath(PROFILE_RECORD, ROOT),
+                         "file": os.path.relpath(record_path, ROOT),
                          "fetch_bytes": traffic.get("fetch_bytes"), "write_bytes": traffic.get("write_bytes"),
                          "rocprof_mean_us": traffic.get("mean_us")},
                      "kernel": names[dom], "kernel_ms_per_launch": round(avg[dom], 5),
@@ -349,7 +362,8 @@ def main() -> int:
         "per_scan_launches": {"gpix_s": round(single_gpix, 3),
                               "scans_s": round(N_SCANS * len(THRESHOLDS) * reps / (single_ms * 1e-3), 1)},
         "batched_scans_s": round(N_SCANS * len(THRESHOLDS) * args.steps / (gpu_ms * 1e-3), 1),
-        "latency_ms": {"workload": "single 64x2048 scan, T=0.5, skip 3, flic_cluster_async",
+        "latency_ms": {"workload": "single 64x2048 scan, T=0.5, skip 3, " + (
+                           f"min {MP} points, flic_cluster_batched (n=1)" if MP else "flic_cluster_async"),
                        "reps": args.latency_reps,
                        "host_p50": round(percentile(lat_host, 0.5), 4),
                        "host_p99": round(percentile(lat_host, 0.99), 4),
