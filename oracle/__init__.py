@@ -42,6 +42,10 @@ def lib() -> ctypes.CDLL:
                                           ctypes.c_float, ctypes.c_int32, ip]
         L.flic_oracle_filter_small.restype = ctypes.c_int32
         L.flic_oracle_filter_small.argtypes = [ip, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ip]
+        L.flic_oracle_ground.restype = ctypes.c_int32
+        L.flic_oracle_ground.argtypes = [fp, ctypes.c_int32, ctypes.c_int32, fp, fp, fp, fp, fp, fp,
+                                         ctypes.c_float, ctypes.c_float,
+                                         ctypes.POINTER(ctypes.c_uint8), fp]
         L.flic_oracle_dist2.restype = ctypes.c_float
         L.flic_oracle_dist2.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
         _lib = L
@@ -71,6 +75,28 @@ def cluster_status(range_img: np.ndarray, cos_v: np.ndarray, cos_h: np.ndarray,
                                    float(threshold), int(skip_depth),
                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return st, out[: H * W].reshape(H, W) if H * W > 0 else out[:0]
+
+
+def ground(range_img: np.ndarray, tables) -> tuple:
+    """Section III.A ground extraction.  tables: an object with float32 [H]
+    arrays sin_a, cos_a, tan_lo, tan_hi, sin_d, cos_d and floats
+    sensor_height, tan_theta.  Returns (ground mask uint8 [H, W], range with
+    ground cells set to 0)."""
+    r = np.ascontiguousarray(range_img, dtype=np.float32)
+    H, W = r.shape
+    arrs = [np.ascontiguousarray(getattr(tables, k), dtype=np.float32)
+            for k in ("sin_a", "cos_a", "tan_lo", "tan_hi", "sin_d", "cos_d")]
+    for a in arrs:
+        if a.shape != (H,):
+            raise ValueError("ground tables must have H entries")
+    mask = np.empty((H, W), dtype=np.uint8)
+    out = np.empty((H, W), dtype=np.float32)
+    st = lib().flic_oracle_ground(_fptr(r), H, W, *[_fptr(a) for a in arrs],
+                                  float(tables.sensor_height), float(tables.tan_theta),
+                                  mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _fptr(out))
+    if st != 0:
+        raise ValueError(f"flic_oracle_ground failed with status {st}")
+    return mask, out
 
 
 def filter_small(labels: np.ndarray, min_points: int) -> np.ndarray:

@@ -165,3 +165,66 @@ int32_t flic_oracle_filter_small(const int32_t* labels, int32_t H, int32_t W,
     free(count);
     return 0;
 }
+
+/* Section III.A, ground extraction, in the paper's order of steps.
+ *   1. Eq. (2): for every pair of vertically adjacent measurements, the
+ *      surface angle beta at the upper cell (range d1) between its beam and
+ *      the surface it spans with the lower cell (range d2):
+ *      tan(beta) = (d2 sin a) / (d1 - d2 cos a), sin a and cos a from the
+ *      tables of the lower cell's row.
+ *   2. The pair spans a horizontal surface when tan(beta) lies in the lower
+ *      row's window [tan_lo, tan_hi] (tangents of the upper beam's angle
+ *      below the horizontal -+ the threshold angle, from the caller).
+ *   3. A cell is tested with the cell above it; the first row has no row
+ *      above and takes the result of the second row's test (the paper
+ *      extends beta_2 to the first channel), and so does any cell whose
+ *      upper neighbour is missing: it takes its pair with the cell below.
+ *   4. Height image: z = sensor_height + d sin(delta_r) over the wheel plane;
+ *      a horizontal cell is ground only when z <= (d cos(delta_r)) tan_theta,
+ *      the slope line from the wheel position.
+ * Every float operation is one binary32 rounding (division included). */
+static int pair_horizontal(const float* range, int32_t W, int32_t r,  /* rows r-1, r */
+                           int32_t c, const float* sin_a, const float* cos_a,
+                           const float* tan_lo, const float* tan_hi) {
+    const float d1 = range[(size_t)(r - 1) * W + c];
+    const float d2 = range[(size_t)r * W + c];
+    if (!is_measurement(d1) || !is_measurement(d2)) return 0;
+    const float num = d2 * sin_a[r];
+    const float den = d1 - d2 * cos_a[r];
+    const float tan_beta = num / den;
+    return tan_lo[r] <= tan_beta && tan_beta <= tan_hi[r];
+}
+
+int32_t flic_oracle_ground(const float* range, int32_t H, int32_t W,
+                           const float* sin_a, const float* cos_a,
+                           const float* tan_lo, const float* tan_hi,
+                           const float* sin_d, const float* cos_d,
+                           float sensor_height, float tan_theta,
+                           uint8_t* ground_out, float* range_out) {
+    if (!range || !sin_a || !cos_a || !tan_lo || !tan_hi || !sin_d || !cos_d) return -1;
+    if (!ground_out || !range_out) return -1;
+    if (H < 1 || W < 1) return -1;
+    if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX) return -1;
+    for (int32_t r = 0; r < H; ++r) {
+        for (int32_t c = 0; c < W; ++c) {
+            const size_t i = (size_t)r * W + c;
+            const float d = range[i];
+            int ground = 0;
+            if (is_measurement(d)) {
+                int horizontal;
+                if (r >= 1 && is_measurement(range[i - W]))
+                    horizontal = pair_horizontal(range, W, r, c, sin_a, cos_a, tan_lo, tan_hi);
+                else
+                    horizontal = r + 1 < H && pair_horizontal(range, W, r + 1, c, sin_a, cos_a, tan_lo, tan_hi);
+                if (horizontal) {
+                    const float z = sensor_height + d * sin_d[r];
+                    const float line = (d * cos_d[r]) * tan_theta;
+                    ground = z <= line;
+                }
+            }
+            ground_out[i] = (uint8_t)ground;
+            range_out[i] = ground ? 0.0f : d;
+        }
+    }
+    return 0;
+}

@@ -19,6 +19,8 @@
  *     of Section III.B.2, taken densely).
  *   - Output: each measurement gets the smallest linear index r*W + c of its
  *     connected component; missing pixels get -1.
+ *   - Ground extraction before clustering (Section III.A): cells on a near
+ *     horizontal surface below a slope line are removed (range 0).
  *   - Optional cluster-size threshold (Section III.B.1, 100 points in the
  *     paper): components with fewer measurements are relabelled -1.
  */
@@ -56,6 +58,26 @@ int32_t flic_oracle_cluster(const float* range, int32_t H, int32_t W,
  * Returns 0, -1 for invalid arguments, -2 when memory runs out.            */
 int32_t flic_oracle_filter_small(const int32_t* labels, int32_t H, int32_t W,
                                  int32_t min_points, int32_t* labels_out);
+
+/* Ground extraction (Section III.A, Eq. 1/2, the height image and the
+ * first-channel rule).  A cell is tested with the cell above it, or, when it
+ * is in the first row or the cell above is missing, takes the test of its
+ * pair with the cell below.  Host arrays; per-row tables of H entries:
+ *   sin_a, cos_a  sin / cos of the angle between rows r-1 and r (entry 0 unused)
+ *   tan_lo, tan_hi  window of tan(beta) for the pair (r-1, r) to span a
+ *                   horizontal surface (entry 0 unused)
+ *   sin_d, cos_d  sin / cos of row r's elevation angle
+ *   sensor_height metres of the sensor above the wheel plane
+ *   tan_theta     slope of the height line (tan 10 degrees in the paper)
+ * ground_out [H][W] gets 1 for a ground cell, else 0; range_out [H][W] is the
+ * range with ground cells set to 0 (removed) and every other value copied.
+ * Returns 0, -1 for invalid arguments, -2 when memory runs out.            */
+int32_t flic_oracle_ground(const float* range, int32_t H, int32_t W,
+                           const float* sin_a, const float* cos_a,
+                           const float* tan_lo, const float* tan_hi,
+                           const float* sin_d, const float* cos_d,
+                           float sensor_height, float tan_theta,
+                           uint8_t* ground_out, float* range_out);
 
 #ifdef __cplusplus
 }

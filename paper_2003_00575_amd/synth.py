@@ -59,6 +59,7 @@ class Scan:
     skip_depth: int
     object_id: Optional[np.ndarray] = None
     seed: Optional[int] = None
+    phi: Optional[np.ndarray] = None      # row elevations (radians, float64), when known
 
     @property
     def H(self) -> int:
@@ -277,7 +278,45 @@ def synth_scan(H: int, W: int, top_deg: float, bottom_deg: float, n_objects: int
     elif dropout != "none":
         raise ValueError(dropout)
     cos_v, cos_h = make_tables(phi, W, skip_depth)
-    return Scan(img, cos_v, cos_h, float(threshold), int(skip_depth), sid, seed)
+    return Scan(img, cos_v, cos_h, float(threshold), int(skip_depth), sid, seed, phi)
+
+
+@dataclasses.dataclass
+class GroundTables:
+    """Per-row sensor tables for ground extraction, float32 [H] each:
+    sin_a / cos_a of the angle between rows r-1 and r, the window
+    [tan_lo, tan_hi] of tan(beta) for that pair to lie on a horizontal
+    surface (entries 0 unused, NaN), sin_d / cos_d of row r's elevation; the
+    sensor height over the wheel plane and the slope of the height line."""
+    sin_a: np.ndarray
+    cos_a: np.ndarray
+    tan_lo: np.ndarray
+    tan_hi: np.ndarray
+    sin_d: np.ndarray
+    cos_d: np.ndarray
+    sensor_height: float
+    tan_theta: float
+
+
+def ground_tables(phi: np.ndarray, theta_deg: float = 10.0,
+                  sensor_height: float = -GROUND_Z) -> GroundTables:
+    """Tables for elevations phi (radians, row 0 = top), computed in double
+    and rounded once to float32.  A horizontal surface meets the upper beam
+    of a row pair at the beam's angle below the horizontal, -phi_{r-1}; the
+    window is that angle -+ theta, its lower end clamped at 0 (a surface
+    angle is never negative)."""
+    H = phi.shape[0]
+    th = math.radians(theta_deg)
+    nan = np.full(H, np.nan)
+    a = phi[:-1] - phi[1:]
+    beam = -phi[:-1]
+    sin_a, cos_a, lo, hi = nan.copy(), nan.copy(), nan.copy(), nan.copy()
+    sin_a[1:], cos_a[1:] = np.sin(a), np.cos(a)
+    lo[1:] = np.tan(np.maximum(beam - th, 0.0))
+    hi[1:] = np.tan(beam + th)
+    f = lambda x: np.asarray(x, dtype=np.float64).astype(np.float32)
+    return GroundTables(f(sin_a), f(cos_a), f(lo), f(hi), f(np.sin(phi)), f(np.cos(phi)),
+                        float(np.float32(sensor_height)), float(np.float32(math.tan(th))))
 
 
 # ---------------------------------------------------------------------------
