@@ -183,6 +183,49 @@ flic_status flic_ctx_bytes_in_use(const flic_ctx* ctx, size_t* bytes);
 flic_status flic_ctx_set_pass_timing(flic_ctx* ctx, int32_t enable);
 flic_status flic_ctx_pass_times(flic_ctx* ctx, float* total_ms, int32_t* n_launches);
 
+/* Ground extraction (Section III.A), the step before clustering.  Sensor
+ * tables (device pointers, H float32 entries each; entry 0 of the first four
+ * is never read):
+ *   sin_a, cos_a   sin / cos of the angle between rows r-1 and r
+ *   tan_lo, tan_hi window of tan(beta) in which the pair (r-1, r) spans a
+ *                  near-horizontal surface: the tangents of the upper beam's
+ *                  angle below the horizontal minus / plus the threshold angle
+ *                  (10 degrees in the paper), the lower end clamped at 0
+ *   sin_d, cos_d   sin / cos of row r's elevation angle
+ *   sensor_height  metres of the sensor above the wheel plane
+ *   tan_theta      slope of the height line (tan 10 degrees in the paper)   */
+typedef struct {
+    const float* sin_a;
+    const float* cos_a;
+    const float* tan_lo;
+    const float* tan_hi;
+    const float* sin_d;
+    const float* cos_d;
+    float sensor_height;
+    float tan_theta;
+} flic_ground_tables;
+
+/* Remove the ground from n_scans range images of one shape taken with one
+ * sensor (stream-ordered on hip_stream, returns at once).  range_in and
+ * range_out are [n_scans][H][W] float32 device buffers that must not
+ * overlap; ground_mask is [n_scans][H][W] uint8 (1 = ground) or null.
+ * A measurement (range > 0 and finite) is ground when
+ *   - Eq. (2), tan(beta) = (d2 sin a) / (d1 - d2 cos a) in binary32 with an
+ *     IEEE division, for the pair it forms with the cell above (d1 above,
+ *     d2 below), lies in that row's [tan_lo, tan_hi]; a cell in the first
+ *     row or under a missing cell takes the pair it forms with the cell below;
+ *   - and it lies below the height line: sensor_height + d sin_d[r] <=
+ *     (d cos_d[r]) tan_theta.
+ * Ground cells get range 0 (removed, as Section III.A treats zeros); every
+ * other value is copied unchanged.  The output feeds the flic_cluster*
+ * entry points.  H, W >= 1, H*W <= INT32_MAX, n_scans 0..65535 (0 is a
+ * no-op; the range pointers may then be null), sensor_height and tan_theta
+ * finite, no overlap between inputs and outputs; FLIC_EINVAL otherwise,
+ * with nothing enqueued.                                                  */
+flic_status flic_ground_remove(flic_ctx* ctx, const float* range_in, int32_t n_scans,
+                               int32_t H, int32_t W, const flic_ground_tables* tables,
+                               float* range_out, uint8_t* ground_mask, void* hip_stream);
+
 /* Message for the last error on this thread ("" if none).                  */
 const char* flic_last_error(void);
 

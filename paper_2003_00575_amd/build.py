@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflic.so")
-SOURCES = [os.path.join(CSRC, "flic_kernels.hip"), os.path.join(CSRC, "flic_api.cpp")]
+SOURCES = [os.path.join(CSRC, "flic_kernels.hip"), os.path.join(CSRC, "flic_api.cpp"),
+           os.path.join(CSRC, "flic_ground.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: the edge test must be a chain of separately rounded
@@ -30,15 +31,16 @@ OBJ_DIR = os.path.join(HERE, "_build")
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the kernels once per tile width and the host API, in
-    parallel, then link libflic.so."""
+    """Compile the clustering kernels once per tile width, the ground
+    kernel and the host API, in parallel, then link libflic.so."""
     os.makedirs(OBJ_DIR, exist_ok=True)
     cmds = []
     for tw in TILE_WIDTHS:
         obj = os.path.join(OBJ_DIR, f"flic_kernels_w{tw}.o")
         cmds.append((obj, [HIPCC, *FLAGS, f"-DFLIC_TILE_W={tw}", "-c", "-o", obj, SOURCES[0]]))
-    api_obj = os.path.join(OBJ_DIR, "flic_api.o")
-    cmds.append((api_obj, [HIPCC, *FLAGS, "-c", "-o", api_obj, SOURCES[1]]))
+    for src in SOURCES[1:]:
+        obj = os.path.join(OBJ_DIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+        cmds.append((obj, [HIPCC, *FLAGS, "-c", "-o", obj, src]))
     procs = []
     for obj, cmd in cmds:
         if verbose:
@@ -56,10 +58,10 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-def device_asm(out_path: str) -> str:
-    """Write the gfx950 assembly of the kernels (for instruction checks)."""
+def device_asm(out_path: str, source: int = 0) -> str:
+    """Write the gfx950 assembly of SOURCES[source] (for instruction checks)."""
     cmd = [HIPCC, *[f for f in FLAGS if f != "-fPIC"], "-S", "--cuda-device-only",
-           "-o", out_path, SOURCES[0]]
+           "-o", out_path, SOURCES[source]]
     subprocess.check_call(cmd)
     return out_path
 

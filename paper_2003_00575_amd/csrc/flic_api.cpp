@@ -669,6 +669,35 @@ flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
     return FLIC_OK;
 }
 
+flic_status flic_ground_remove(flic_ctx* ctx, const float* range_in, int32_t n_scans,
+                               int32_t H, int32_t W, const flic_ground_tables* t,
+                               float* range_out, uint8_t* ground_mask, void* hip_stream) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    if (!t || !t->sin_a || !t->cos_a || !t->tan_lo || !t->tan_hi || !t->sin_d || !t->cos_d)
+        return fail(FLIC_EINVAL, "null table pointer");
+    if (n_scans < 0 || n_scans > 65535) return fail(FLIC_EINVAL, "n_scans %d outside 0..65535", n_scans);
+    if (H < 1 || W < 1) return fail(FLIC_EINVAL, "H=%d W=%d", H, W);
+    if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX) return fail(FLIC_EINVAL, "H*W exceeds INT32_MAX");
+    if (!std::isfinite(t->sensor_height) || !std::isfinite(t->tan_theta))
+        return fail(FLIC_EINVAL, "sensor_height and tan_theta must be finite");
+    if (n_scans == 0) return FLIC_OK;                // nothing to read or write
+    if (!range_in || !range_out) return fail(FLIC_EINVAL, "null range pointer");
+    const size_t px = (size_t)n_scans * H * W;
+    if (overlaps(range_in, px * 4, range_out, px * 4))
+        return fail(FLIC_EINVAL, "range_in and range_out overlap");
+    if (ground_mask && (overlaps(ground_mask, px, range_in, px * 4) || overlaps(ground_mask, px, range_out, px * 4)))
+        return fail(FLIC_EINVAL, "ground_mask overlaps a range buffer");
+    for (const float* tab : {t->sin_a, t->cos_a, t->tan_lo, t->tan_hi, t->sin_d, t->cos_d})
+        if (overlaps(tab, (size_t)H * 4, range_out, px * 4) ||
+            (ground_mask && overlaps(tab, (size_t)H * 4, ground_mask, px)))
+            return fail(FLIC_EINVAL, "a table overlaps an output");
+    HIP_TRY(set_device(ctx->device));
+    flic::GroundArgs a{range_in, range_out, ground_mask, t->sin_a, t->cos_a, t->tan_lo, t->tan_hi,
+                       t->sin_d, t->cos_d, t->sensor_height, t->tan_theta, H, W};
+    HIP_TRY(flic::launch_ground(a, n_scans, static_cast<hipStream_t>(hip_stream)));
+    return FLIC_OK;
+}
+
 void flic_plan_destroy(flic_plan* plan) {
     if (!plan) return;
     (void)set_device(plan->ctx->device);

@@ -114,4 +114,25 @@ hipError_t launch_cluster_tw(const BatchRef& ref, int skip, bool sized, int n_ti
                              hipStream_t stream, hipEvent_t* events);
 
 
+
+// Ground extraction over n scans of one shape sharing one sensor's tables:
+// range_in / range_out / mask are [n][H][W] (mask may be null); the tables
+// have H entries each.
+struct GroundArgs {
+    const float* range_in;
+    float* range_out;
+    uint8_t* mask;
+    const float* sin_a;
+    const float* cos_a;
+    const float* tan_lo;
+    const float* tan_hi;
+    const float* sin_d;
+    const float* cos_d;
+    float sensor_height;
+    float tan_theta;
+    int32_t H, W;
+};
+
+hipError_t launch_ground(const GroundArgs& a, int n_scans, hipStream_t stream);
+
 }  // namespace flic

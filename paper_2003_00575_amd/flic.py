@@ -38,6 +38,12 @@ class _Scan(ctypes.Structure):
                 ("min_points", ctypes.c_int32)]
 
 
+class _GroundTables(ctypes.Structure):
+    _fields_ = [("sin_a", ctypes.c_void_p), ("cos_a", ctypes.c_void_p), ("tan_lo", ctypes.c_void_p),
+                ("tan_hi", ctypes.c_void_p), ("sin_d", ctypes.c_void_p), ("cos_d", ctypes.c_void_p),
+                ("sensor_height", ctypes.c_float), ("tan_theta", ctypes.c_float)]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -56,6 +62,8 @@ def lib() -> ctypes.CDLL:
     L.flic_ctx_create.restype = i32
     L.flic_ctx_destroy.argtypes = [vp]
     L.flic_ctx_destroy.restype = None
+    L.flic_ground_remove.argtypes = [vp, vp, i32, i32, i32, ctypes.POINTER(_GroundTables), vp, vp, vp]
+    L.flic_ground_remove.restype = i32
     L.flic_cluster.argtypes = [vp, i32, i32, ctypes.POINTER(_Tables), f32, i32, vp]
     L.flic_cluster.restype = i32
     L.flic_cluster_async.argtypes = [vp, vp, i32, i32, ctypes.POINTER(_Tables), f32, i32, vp, vp]
@@ -366,6 +374,67 @@ def cluster_batched(scans: Sequence[DeviceScan], stream=None):
     if not scans:
         return []
     return default_context(scans[0].range_img.device.index).cluster_batched(scans, stream)
+
+
+@dataclasses.dataclass
+class DeviceGroundTables:
+    """Device copies (float32 [H] tensors) of one sensor's ground tables."""
+    sin_a: "object"
+    cos_a: "object"
+    tan_lo: "object"
+    tan_hi: "object"
+    sin_d: "object"
+    cos_d: "object"
+    sensor_height: float
+    tan_theta: float
+
+    @property
+    def H(self) -> int:
+        return int(self.sin_a.shape[0])
+
+    def to_c(self) -> _GroundTables:
+        import torch
+        for k in ("sin_a", "cos_a", "tan_lo", "tan_hi", "sin_d", "cos_d"):
+            _check_tensor(getattr(self, k), torch.float32, (self.H,), k)
+        return _GroundTables(self.sin_a.data_ptr(), self.cos_a.data_ptr(), self.tan_lo.data_ptr(),
+                             self.tan_hi.data_ptr(), self.sin_d.data_ptr(), self.cos_d.data_ptr(),
+                             float(self.sensor_height), float(self.tan_theta))
+
+
+def ground_tables_to_device(g, device="cuda") -> DeviceGroundTables:
+    """Copy host ground tables (synth.GroundTables) to the device."""
+    import torch
+    t = {k: torch.from_numpy(getattr(g, k)).to(device)
+         for k in ("sin_a", "cos_a", "tan_lo", "tan_hi", "sin_d", "cos_d")}
+    return DeviceGroundTables(**t, sensor_height=g.sensor_height, tan_theta=g.tan_theta)
+
+
+def ground_remove(range_img, tables: DeviceGroundTables, out=None, mask=None, stream=None,
+                  ctx: Optional["Context"] = None, with_mask: bool = True):
+    """flic_ground_remove on a [H, W] or [n, H, W] float32 device tensor:
+    returns (range with ground cells set to 0, uint8 ground mask or None)."""
+    import torch
+    squeeze = range_img.dim() == 2
+    r = range_img.unsqueeze(0) if squeeze else range_img
+    n, H, W = r.shape
+    _check_tensor(r, torch.float32, (n, H, W), "range_img")
+    if out is None:
+        out = torch.empty_like(r)
+    out = out.view(n, H, W)
+    _check_tensor(out, torch.float32, (n, H, W), "out")
+    if mask is None and with_mask:
+        mask = torch.empty((n, H, W), dtype=torch.uint8, device=r.device)
+    if mask is not None:
+        mask = mask.view(n, H, W)
+        _check_tensor(mask, torch.uint8, (n, H, W), "mask")
+    ctx = ctx or default_context(r.device.index)
+    t = tables.to_c()
+    _check(lib().flic_ground_remove(ctx.handle, r.data_ptr(), n, H, W, ctypes.byref(t), out.data_ptr(),
+                                    mask.data_ptr() if mask is not None else None,
+                                    _stream_handle(stream)))
+    if squeeze:
+        return out[0], (mask[0] if mask is not None else None)
+    return out, mask
 
 
 def to_device(scan, device="cuda", min_points: int = 0) -> DeviceScan:

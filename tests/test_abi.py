@@ -87,3 +87,23 @@ def test_scan_struct_layout_matches_header(tmp_path):
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(flic._Scan)] + [getattr(flic._Scan, f).offset for f in fields]
     assert got == want
+
+
+def test_ground_tables_struct_layout_matches_header(tmp_path):
+    import ctypes
+    import subprocess
+    from paper_2003_00575_amd import flic
+    src = tmp_path / "glayout.c"
+    fields = [f for f, _ in flic._GroundTables._fields_]
+    body = "\n".join(f'    printf("%zu\\n", offsetof(flic_ground_tables, {f}));' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "flic.h"\nint main(void) {\n'
+                   f'    printf("%zu\\n", sizeof(flic_ground_tables));\n{body}\n    return 0;\n}}\n')
+    exe = tmp_path / "glayout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(flic._GroundTables)] + [getattr(flic._GroundTables, f).offset for f in fields]
+    assert got == want
+
+
+def test_ground_remove_rejects_null_ctx(L):
+    assert L.flic_ground_remove(None, None, 1, 4, 4, None, None, None, None) == flic.FLIC_EINVAL

@@ -1,0 +1,145 @@
+"""Ground extraction (Section III.A) on the GPU vs the CPU oracle, bit for bit
+(ground mask and output range, through the C ABI): the large batch in one call,
+scans of every shape class with their own tables, ragged sizes (rows not a
+multiple of the 16-row lane walk, columns not a multiple of the 256-column
+workgroup), special values, noise-free ground and vertical faces, the
+first-row and missing-above rules, argument errors, and ground removal
+followed by clustering (with and without the size threshold)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_00575_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def flic():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_00575_amd import flic as f
+    f.lib()
+    return f
+
+
+def _run(flic, imgs, g, with_mask=True):
+    """imgs: [n, H, W] float32 host array; returns (mask, out) host arrays."""
+    d = torch.from_numpy(np.ascontiguousarray(imgs)).cuda()
+    dt = flic.ground_tables_to_device(g)
+    out, mask = flic.ground_remove(d, dt, with_mask=with_mask)
+    torch.cuda.synchronize()
+    return (None if mask is None else mask.cpu().numpy()), out.cpu().numpy()
+
+
+def _assert_same(flic, imgs, g, what):
+    mask, out = _run(flic, imgs, g)
+    for i in range(imgs.shape[0]):
+        wm, wo = oracle.ground(imgs[i], g)
+        if not np.array_equal(mask[i], wm):
+            bad = np.argwhere(mask[i] != wm)
+            raise AssertionError(f"{what} scan {i}: {len(bad)} mask cells differ, first {tuple(bad[0])}")
+        if not np.array_equal(out[i].view(np.uint32), wo.view(np.uint32)):
+            raise AssertionError(f"{what} scan {i}: output ranges differ")
+
+
+def test_large_batch_one_call(flic):
+    scans = [synth.large_batch_scan(i, 0.5) for i in range(64)]
+    g = synth.ground_tables(scans[0].phi)
+    imgs = np.stack([s.range_img for s in scans])
+    _assert_same(flic, imgs, g, "large batch")
+    mask, _ = _run(flic, imgs, g)
+    assert mask.sum() > 0
+
+
+@pytest.mark.parametrize("i", range(5))
+def test_shape_classes_own_tables(flic, i):
+    s = synth.mixed_scan(i)
+    g = synth.ground_tables(s.phi)
+    _assert_same(flic, s.range_img[None], g, f"mixed {s.H}x{s.W}")
+
+
+@pytest.mark.parametrize("H, W", [(1, 5), (2, 3), (15, 255), (16, 256), (17, 257), (33, 1000),
+                                  (100, 77), (129, 2049), (300, 40)])
+def test_ragged_sizes_random_tables(flic, H, W):
+    rng = np.random.default_rng(H * 7919 + W)
+    top = rng.uniform(-5.0, 10.0)
+    phi = np.deg2rad(top - np.concatenate([[0.0], np.cumsum(rng.uniform(0.05, 1.0, size=H - 1))]))
+    g = synth.ground_tables(phi, theta_deg=float(rng.uniform(5.0, 15.0)),
+                            sensor_height=float(rng.uniform(1.0, 2.5)))
+    t, _ = synth.raycast(phi, W, synth._draw_objects(8, rng))
+    img = np.where(t <= synth.MAX_RANGE, t + rng.normal(0.0, 0.02, size=t.shape), 0.0).astype(np.float32)
+    img[rng.uniform(size=img.shape) < 0.15] = 0.0
+    _assert_same(flic, np.stack([img, img[::-1].copy(), np.roll(img, 3, axis=1)]), g, f"{H}x{W}")
+
+
+def test_special_values_and_mask_optional(flic):
+    s = synth.single_scan(2)
+    g = synth.ground_tables(s.phi)
+    img = s.range_img.copy()
+    specials = np.array([0.0, -0.0, -1.0, np.nan, np.inf, -np.inf, 1e-42, 3e38], dtype=np.float32)
+    img[10:14, :8] = specials
+    img[40, 100:200] = np.nan
+    _assert_same(flic, img[None], g, "specials")
+    mask, out = _run(flic, img[None], g, with_mask=False)
+    assert mask is None
+    _, wo = oracle.ground(img, g)
+    assert np.array_equal(out[0].view(np.uint32), wo.view(np.uint32))
+
+
+def test_flat_ground_and_vertical_faces(flic):
+    phi = synth.elevations(64, 2.0, -24.8)
+    g = synth.ground_tables(phi)
+    t, _ = synth.raycast(phi, 2048, [])
+    flat = np.where(t <= synth.MAX_RANGE, t, 0.0).astype(np.float32)
+    mask, out = _run(flic, flat[None], g)
+    assert (mask[0][flat > 0] == 1).all() and (out == 0).all()
+    objs = [synth._Obj(1, 10.0 * math.cos(b), 10.0 * math.sin(b), 0.8, 0.0, 4.0, 0.0, 0.8)
+            for b in np.linspace(0.0, 6.0, 12)]
+    t, sid = synth.raycast(phi, 2048, objs)
+    img = np.where(t <= synth.MAX_RANGE, t, 0.0).astype(np.float32)
+    _assert_same(flic, img[None], g, "vertical faces")
+    mask, _ = _run(flic, img[None], g)
+    assert (mask[0][(sid > 0) & (img > 0)] == 0).all()
+
+
+def test_argument_errors(flic):
+    s = synth.single_scan(1)
+    g = flic.ground_tables_to_device(synth.ground_tables(s.phi))
+    d = torch.from_numpy(s.range_img).cuda()
+    with pytest.raises(flic.FlicError):
+        flic.ground_remove(d, g, out=d)                      # in place: range_in and range_out overlap
+    g_bad = flic.DeviceGroundTables(g.sin_a, g.cos_a, g.tan_lo, g.tan_hi, g.sin_d, g.cos_d,
+                                    g.sensor_height, float("inf"))
+    with pytest.raises(flic.FlicError):
+        flic.ground_remove(d, g_bad)
+    empty = torch.empty((0, s.H, s.W), dtype=torch.float32, device="cuda")
+    out, mask = flic.ground_remove(empty, g)
+    assert out.shape == (0, s.H, s.W)
+
+
+@pytest.mark.parametrize("m", [0, 100])
+def test_ground_then_cluster(flic, m):
+    scans = [synth.large_batch_scan(i, 0.5) for i in range(8)]
+    g = synth.ground_tables(scans[0].phi)
+    imgs = np.stack([s.range_img for s in scans])
+    d = torch.from_numpy(imgs).cuda()
+    out, _ = flic.ground_remove(d, flic.ground_tables_to_device(g), with_mask=False)
+    ctx = flic.Context(0)
+    devs = []
+    for i, s in enumerate(scans):
+        devs.append(flic.DeviceScan(out[i], torch.from_numpy(s.cos_v).cuda(), torch.from_numpy(s.cos_h).cuda(),
+                                    s.threshold, s.skip_depth, None, m))
+    ctx.cluster_batched(devs)
+    torch.cuda.synchronize()
+    for i, s in enumerate(scans):
+        _, wo = oracle.ground(s.range_img, g)
+        want = oracle.cluster(wo, s.cos_v, s.cos_h, s.threshold, s.skip_depth, m)
+        got = devs[i].labels.cpu().numpy()
+        assert np.array_equal(got, want), f"scan {i}: {(got != want).sum()} labels differ"
+        if m == 0:
+            # the ground no longer joins objects: more components than before
+            assert len(np.unique(want)) > len(np.unique(oracle.cluster_scan(s)))
