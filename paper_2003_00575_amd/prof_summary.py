@@ -28,8 +28,10 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "flic_kernels.hip")
+GROUND_SOURCE = os.path.join(HERE, "csrc", "flic_ground.hip")
 COPY_BYTES = 128 << 20          # the calibration copy: 128 MiB read, 128 MiB written
-PASSES = (("tile_label", "k_tile_label"), ("border_merge", "k_scan_merge"), ("relabel", "k_relabel"))
+PASSES = (("tile_label", "k_tile_label"), ("border_merge", "k_scan_merge"), ("relabel", "k_relabel"),
+          ("ground", "k_ground"))
 
 
 def _short(name: str) -> str:
@@ -37,9 +39,14 @@ def _short(name: str) -> str:
     return name.replace("void ", "")[:60]
 
 
-def kernel_source_sha256() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
+def kernel_source_sha256(path: str = KERNEL_SOURCE) -> str:
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
+
+
+def source_sha_for(pass_name: str) -> str:
+    """SHA-256 of the source file that holds the named pass's kernel."""
+    return kernel_source_sha256(GROUND_SOURCE if pass_name == "ground" else KERNEL_SOURCE)
 
 
 def durations(d: str) -> dict:
@@ -130,10 +137,12 @@ def record(args) -> str:
             entry["sq"] = {c: round(x, 1) for c, x in sorted(sq[skey].items())}
         kernels[short] = entry
     sha = kernel_source_sha256()
+    gsha = kernel_source_sha256(GROUND_SOURCE)
     lines = [f"# rocprofv3 record: {args.workload}",
              "# commands (repository root; the profiled program is bench.py):"]
     lines += [f"#   {c}" for c in args.command]
     lines += [f"# kernel source: paper_2003_00575_amd/csrc/flic_kernels.hip sha256 {sha}",
+              f"# ground kernel source: paper_2003_00575_amd/csrc/flic_ground.hip sha256 {gsha}",
               f"# byte calibration (plain 128 MiB device copy in the same program): FETCH_SIZE "
               f"{fetch_copy_kib:.0f} KiB -> x{f_fetch:.3f}, WRITE_SIZE {write_copy_kib:.0f} KiB -> x{f_write:.3f}",
               "",
@@ -150,6 +159,7 @@ def record(args) -> str:
             if "sq" in e:
                 lines.append(f"{short:13s} " + "  ".join(f"{c}={x:.4g}" for c, x in e["sq"].items()))
     lines += ["", "json: " + json.dumps({"workload": args.workload, "kernel_source_sha256": sha,
+                                          "ground_source_sha256": gsha,
                                           "fetch_factor": round(f_fetch, 4), "write_factor": round(f_write, 4),
                                           "kernels": kernels}, sort_keys=True)]
     return "\n".join(lines) + "\n"
