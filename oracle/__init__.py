@@ -40,6 +40,9 @@ def lib() -> ctypes.CDLL:
         L.flic_oracle_cluster.restype = ctypes.c_int32
         L.flic_oracle_cluster.argtypes = [fp, ctypes.c_int32, ctypes.c_int32, fp, fp,
                                           ctypes.c_float, ctypes.c_int32, ip]
+        L.flic_oracle_cluster_maps.restype = ctypes.c_int32
+        L.flic_oracle_cluster_maps.argtypes = [fp, ctypes.c_int32, ctypes.c_int32, fp, fp,
+                                               ctypes.c_float, ctypes.c_int32, ctypes.c_int32, ip]
         L.flic_oracle_filter_small.restype = ctypes.c_int32
         L.flic_oracle_filter_small.argtypes = [ip, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ip]
         L.flic_oracle_ground.restype = ctypes.c_int32
@@ -114,15 +117,27 @@ def filter_small(labels: np.ndarray, min_points: int) -> np.ndarray:
 
 
 def cluster(range_img: np.ndarray, cos_v: np.ndarray, cos_h: np.ndarray,
-            threshold: float, skip_depth: int, min_points: int = 0) -> np.ndarray:
+            threshold: float, skip_depth: int, min_points: int = 0, maps: int = 0) -> np.ndarray:
     """Labels int32 [H, W]: minimum linear index of each component, -1 if
-    missing or (min_points > 0) in a component of fewer than min_points pixels."""
-    st, out = cluster_status(range_img, cos_v, cos_h, threshold, skip_depth)
+    missing or (min_points > 0) in a component of fewer than min_points pixels.
+    maps = 1 takes the skip edges from the stride-k maps of Section III.B.2
+    instead of every pixel."""
+    if maps:
+        r = np.ascontiguousarray(range_img, dtype=np.float32)
+        H, W = r.shape
+        out = np.empty((H, W), dtype=np.int32)
+        st = lib().flic_oracle_cluster_maps(_fptr(r), H, W,
+                                            _fptr(np.ascontiguousarray(cos_v, dtype=np.float32)),
+                                            _fptr(np.ascontiguousarray(cos_h, dtype=np.float32)),
+                                            float(threshold), int(skip_depth), int(maps),
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    else:
+        st, out = cluster_status(range_img, cos_v, cos_h, threshold, skip_depth)
     if st != 0:
         raise ValueError(f"flic_oracle_cluster failed with status {st}")
     return filter_small(out, min_points) if min_points > 0 else out
 
 
-def cluster_scan(scan, min_points: int = 0) -> np.ndarray:
+def cluster_scan(scan, min_points: int = 0, maps: int = 0) -> np.ndarray:
     return cluster(scan.range_img, scan.cos_v, scan.cos_h, scan.threshold, scan.skip_depth,
-                   min_points)
+                   min_points, maps)

@@ -46,10 +46,29 @@ static int connected(float d1, float d2, float cos_alpha, float t2) {
     return d2sq <= t2;
 }
 
+/* Section III.B.2, the paper's own Map Connections: a map of stride k holds
+ * the points whose row and column are both multiples of k, and connects each
+ * with its k-th neighbour to the right and below.  A skip edge of offset k is
+ * present only when its first end (the upper or left one) lies on that map. */
+static int on_map(int32_t r, int32_t c, int32_t k) { return r % k == 0 && c % k == 0; }
+
+int32_t flic_oracle_cluster_maps(const float* range, int32_t H, int32_t W,
+                                 const float* cos_v, const float* cos_h,
+                                 float threshold, int32_t skip_depth, int32_t maps,
+                                 int32_t* labels_out);
+
 int32_t flic_oracle_cluster(const float* range, int32_t H, int32_t W,
                             const float* cos_v, const float* cos_h,
                             float threshold, int32_t skip_depth,
                             int32_t* labels_out) {
+    return flic_oracle_cluster_maps(range, H, W, cos_v, cos_h, threshold, skip_depth, 0, labels_out);
+}
+
+int32_t flic_oracle_cluster_maps(const float* range, int32_t H, int32_t W,
+                                 const float* cos_v, const float* cos_h,
+                                 float threshold, int32_t skip_depth, int32_t maps,
+                                 int32_t* labels_out) {
+    if (maps != 0 && maps != 1) return -1;
     if (!range || !cos_v || !cos_h || !labels_out) return -1;
     if (H < 1 || W < 1) return -1;
     if (skip_depth < 1 || skip_depth > 8) return -1;
@@ -77,6 +96,7 @@ int32_t flic_oracle_cluster(const float* range, int32_t H, int32_t W,
         for (int32_t c = 0; c < W; ++c) {
             const int32_t p = r * W + c;
             for (int32_t k = 1; k <= N; ++k) {
+                if (maps && k >= 2 && !on_map(r, c, k)) continue;
                 /* vertical: (r, c) -- (r+k, c), angle between rows r, r+k */
                 if (r + k < H) {
                     const int32_t q = p + k * W;

@@ -51,6 +51,16 @@ int32_t flic_oracle_cluster(const float* range, int32_t H, int32_t W,
                             float threshold, int32_t skip_depth,
                             int32_t* labels_out);
 
+/* The same with the choice of skip edges: maps == 0 gives the dense skip
+ * connections above (every pixel, offsets 2..N); maps == 1 the paper's Map
+ * Connections (Section III.B.2): for each stride k = 2..N, only pixels whose
+ * row and column are multiples of k connect to their k-th neighbour to the
+ * right (with wrap) and below.  Direct (k = 1) edges are the same in both. */
+int32_t flic_oracle_cluster_maps(const float* range, int32_t H, int32_t W,
+                                 const float* cos_v, const float* cos_h,
+                                 float threshold, int32_t skip_depth, int32_t maps,
+                                 int32_t* labels_out);
+
 /* Cluster-size threshold (Section III.B.1): every pixel whose label occurs
  * fewer than min_points times in `labels` becomes -1; others keep their
  * label.  labels is host [H][W] int32 with entries -1 or in [0, H*W);
