@@ -72,7 +72,13 @@ typedef struct {
  *              components with fewer measurements are labelled -1 (1 keeps
  *              every component but still runs the counting kernels);
  *              < 0 is FLIC_EINVAL.  The library then also keeps an
- *              [H][W] int32 count array in its scratch.                   */
+ *              [H][W] int32 count array in its scratch.
+ *   map_connections  0: skip edges from every pixel (offsets 2..N along
+ *              both axes); 1: the paper's Map Connections (Section
+ *              III.B.2): for each stride k = 2..N, only pixels whose row
+ *              and column are multiples of k connect to their k-th
+ *              neighbour to the right (with wrap) and below.  Other values
+ *              are FLIC_EINVAL.  With skip_depth 1 both are the same.      */
 typedef struct {
     const float* range_img;
     int32_t H;
@@ -82,6 +88,7 @@ typedef struct {
     int32_t skip_depth;
     int32_t* labels_out;
     int32_t min_points;
+    int32_t map_connections;
 } flic_scan;
 
 typedef struct flic_ctx flic_ctx;
@@ -129,8 +136,9 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n,
                              flic_plan** out);
 
 /* Launch a plan on `hip_stream` for `scans`, which must match the plan's
- * shapes entry by entry: the same H, W, skip_depth, and min_points zero
- * where the plan's is zero, positive where it is positive.  Pointers,
+ * shapes entry by entry: the same H, W, skip_depth and map_connections,
+ * and min_points zero where the plan's is zero, positive where it is
+ * positive.  Pointers,
  * thresholds and positive min_points values may differ: changed
  * descriptors are uploaded before the graph launch.  FLIC_EINVAL on a
  * shape mismatch.                                                          */

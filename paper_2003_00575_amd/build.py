@@ -31,13 +31,16 @@ OBJ_DIR = os.path.join(HERE, "_build")
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the clustering kernels once per tile width, the ground
-    kernel and the host API, in parallel, then link libflic.so."""
+    """Compile the clustering kernels once per tile width and skip-edge
+    mode, the ground kernel and the host API, in parallel, then link
+    libflic.so."""
     os.makedirs(OBJ_DIR, exist_ok=True)
     cmds = []
     for tw in TILE_WIDTHS:
-        obj = os.path.join(OBJ_DIR, f"flic_kernels_w{tw}.o")
-        cmds.append((obj, [HIPCC, *FLAGS, f"-DFLIC_TILE_W={tw}", "-c", "-o", obj, SOURCES[0]]))
+        for maps in (0, 1):
+            obj = os.path.join(OBJ_DIR, f"flic_kernels_w{tw}_m{maps}.o")
+            cmds.append((obj, [HIPCC, *FLAGS, f"-DFLIC_TILE_W={tw}", f"-DFLIC_MAPS={maps}", "-c", "-o", obj,
+                               SOURCES[0]]))
     for src in SOURCES[1:]:
         obj = os.path.join(OBJ_DIR, os.path.splitext(os.path.basename(src))[0] + ".o")
         cmds.append((obj, [HIPCC, *FLAGS, "-c", "-o", obj, src]))

@@ -78,6 +78,8 @@ flic_status check_scans(const flic_scan* scans, int32_t n) {
                                     s.labels_out, i);
         if (st != FLIC_OK) return st;
         if (s.min_points < 0) return fail(FLIC_EINVAL, "scan %d: min_points %d < 0", i, s.min_points);
+        if (s.map_connections != 0 && s.map_connections != 1)
+            return fail(FLIC_EINVAL, "scan %d: map_connections %d not 0 or 1", i, s.map_connections);
     }
     // no scan may write into another scan's buffers
     for (int32_t i = 0; i < n; ++i) {
@@ -93,13 +95,16 @@ flic_status check_scans(const flic_scan* scans, int32_t n) {
     return FLIC_OK;
 }
 
-hipError_t launch_cluster(const flic::BatchRef& ref, int tile_w, int skip, bool sized, int n_tiles,
-                          int n_scans, hipStream_t stream, hipEvent_t* events = nullptr) {
+hipError_t launch_cluster(const flic::BatchRef& ref, int tile_w, int skip, bool sized, bool maps,
+                          int n_tiles, int n_scans, hipStream_t stream, hipEvent_t* events = nullptr) {
     if (n_tiles <= 0 || n_scans <= 0) return hipSuccess;
-    switch (tile_w) {
-        case 64: return flic::launch_cluster_tw<64>(ref, skip, sized, n_tiles, n_scans, stream, events);
-        case 128: return flic::launch_cluster_tw<128>(ref, skip, sized, n_tiles, n_scans, stream, events);
-        case 256: return flic::launch_cluster_tw<256>(ref, skip, sized, n_tiles, n_scans, stream, events);
+    switch (tile_w * 2 + (maps ? 1 : 0)) {
+        case 128: return flic::launch_cluster_tw<64, false>(ref, skip, sized, n_tiles, n_scans, stream, events);
+        case 129: return flic::launch_cluster_tw<64, true>(ref, skip, sized, n_tiles, n_scans, stream, events);
+        case 256: return flic::launch_cluster_tw<128, false>(ref, skip, sized, n_tiles, n_scans, stream, events);
+        case 257: return flic::launch_cluster_tw<128, true>(ref, skip, sized, n_tiles, n_scans, stream, events);
+        case 512: return flic::launch_cluster_tw<256, false>(ref, skip, sized, n_tiles, n_scans, stream, events);
+        case 513: return flic::launch_cluster_tw<256, true>(ref, skip, sized, n_tiles, n_scans, stream, events);
         default: return hipErrorInvalidValue;
     }
 }
@@ -147,10 +152,11 @@ struct flic_plan {
     flic_ctx* ctx = nullptr;
     int32_t n = 0;
     std::vector<flic_scan> shapes;     // shapes as planned
-    struct Group {                     // scans sharing tile width, skip depth and sizing
+    struct Group {                     // scans sharing tile width, skip depth, sizing and skip-edge mode
         int tile_w;
         int skip;
         bool sized;
+        bool maps;
         int n_tiles;
         size_t desc_off;               // byte offset of ScanDesc[members] in the blob
         std::vector<int> members;      // scan indices
@@ -182,6 +188,8 @@ int choose_tile_w(const flic_ctx* ctx, int32_t H, int32_t W, int32_t N) {
 }
 
 bool sized(const flic_scan& s) { return s.min_points > 0; }
+// Map Connections matter only with skip edges (N >= 2).
+bool maps(const flic_scan& s) { return s.map_connections != 0 && s.skip_depth >= 2; }
 
 ScanDesc make_desc(const flic_scan& s, int tile_w, int32_t tile_begin, char* scratch) {
     ScanDesc d{};
@@ -229,7 +237,7 @@ struct Layout {
     std::vector<char> blob;
     struct G {
         int tile_w, skip;
-        bool sized;
+        bool sized, maps;
         int n_tiles;
         size_t desc_off, map_off;
         std::vector<int> members;
@@ -249,12 +257,14 @@ void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, char* 
                                     sized(scans[i])).total;
     }
     const int widths[3] = {64, 128, 256};
-    for (int gi = 0; gi < 2 * 3 * FLIC_MAX_SKIP; ++gi) {
-        const int gw = gi % (3 * FLIC_MAX_SKIP);
-        Layout::G g{widths[gw / FLIC_MAX_SKIP], 1 + gw % FLIC_MAX_SKIP, gi >= 3 * FLIC_MAX_SKIP, 0, 0, 0, {}};
+    constexpr int kShapes = 3 * FLIC_MAX_SKIP;
+    for (int gi = 0; gi < 4 * kShapes; ++gi) {
+        const int gw = gi % kShapes, mode = gi / kShapes;
+        Layout::G g{widths[gw / FLIC_MAX_SKIP], 1 + gw % FLIC_MAX_SKIP, (mode & 1) != 0, (mode & 2) != 0,
+                    0, 0, 0, {}};
         for (int32_t i = 0; i < n; ++i)
             if (choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth) == g.tile_w &&
-                scans[i].skip_depth == g.skip && sized(scans[i]) == g.sized)
+                scans[i].skip_depth == g.skip && sized(scans[i]) == g.sized && maps(scans[i]) == g.maps)
                 g.members.push_back(i);
         if (g.members.empty()) continue;
         std::vector<ScanDesc> descs;
@@ -307,7 +317,7 @@ flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t st
         hipError_t e;
         hipEvent_t* ev = timing_events(timing_ctx, &e);
         HIP_TRY(e);
-        HIP_TRY(launch_cluster(ref, g.tile_w, g.skip, g.sized, g.n_tiles, (int)g.members.size(),
+        HIP_TRY(launch_cluster(ref, g.tile_w, g.skip, g.sized, g.maps, g.n_tiles, (int)g.members.size(),
                                stream, ev));
     }
     return FLIC_OK;
@@ -491,7 +501,7 @@ flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img, int32_t H,
     if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
     flic_status st = check_scan(range_img, H, W, alpha_tables, threshold, skip_depth, labels_out, 0);
     if (st != FLIC_OK) return st;
-    const flic_scan s{range_img, H, W, *alpha_tables, threshold, skip_depth, labels_out, 0};
+    const flic_scan s{range_img, H, W, *alpha_tables, threshold, skip_depth, labels_out, 0, 0};
     const int tw = choose_tile_w(ctx, H, W, skip_depth);
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(set_device(ctx->device));
@@ -503,7 +513,7 @@ flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img, int32_t H,
     hipError_t e;
     hipEvent_t* ev = timing_events(ctx, &e);
     HIP_TRY(e);
-    HIP_TRY(launch_cluster(ref, tw, skip_depth, false, ref.one.tiles_x * ref.one.tiles_y, 1, stream, ev));
+    HIP_TRY(launch_cluster(ref, tw, skip_depth, false, false, ref.one.tiles_x * ref.one.tiles_y, 1, stream, ev));
     HIP_TRY(hipEventRecord(slot->done, stream));
     slot->pending = true;
     return FLIC_OK;
@@ -587,7 +597,7 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, f
     build_layout(ctx, scans, n, static_cast<char*>(p->scratch), L);
     p->blob_bytes = L.blob.size();
     for (const auto& g : L.groups)
-        p->groups.push_back({g.tile_w, g.skip, g.sized, g.n_tiles, g.desc_off, g.members});
+        p->groups.push_back({g.tile_w, g.skip, g.sized, g.maps, g.n_tiles, g.desc_off, g.members});
     if (hipMalloc(&p->dev_mem, p->blob_bytes) != hipSuccess) {
         p->dev_mem = nullptr;
         return cleanup(fail(FLIC_ENOMEM, "hipMalloc(%zu) failed", p->blob_bytes));
@@ -633,6 +643,8 @@ flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
         if (sized(a) != sized(b))
             return fail(FLIC_EINVAL, "scan %d: min_points %s 0 in the plan but %d now", i,
                         sized(b) ? ">" : "==", a.min_points);
+        if (maps(a) != maps(b))
+            return fail(FLIC_EINVAL, "scan %d: map_connections differs from the plan", i);
     }
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(set_device(plan->ctx->device));

@@ -106,10 +106,11 @@ constexpr int kPasses = 3;
 // Enqueue the three passes (tile labelling, scan merge, relabel) for
 // `n_scans` scans with `n_tiles` tiles in total, of tile width TW (64, 128
 // or 256) and skip depth `skip` (1..kMaxSkip); `sized` selects the kernels
-// that also count component sizes and apply each scan's min_points.  When
-// `events` is non-null, events[0] is recorded before the first pass and
+// that also count component sizes and apply each scan's min_points; MAPS the
+// skip edges of the stride-k maps (Section III.B.2) instead of every pixel's.
+// When `events` is non-null, events[0] is recorded before the first pass and
 // events[i + 1] after pass i.
-template <int TW>
+template <int TW, bool MAPS>
 hipError_t launch_cluster_tw(const BatchRef& ref, int skip, bool sized, int n_tiles, int n_scans,
                              hipStream_t stream, hipEvent_t* events);
 

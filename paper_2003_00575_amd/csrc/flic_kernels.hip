@@ -212,7 +212,10 @@ __device__ __forceinline__ bool border_slot(int it, int tw, int th, int& rr, int
 // SIZE (scans with a cluster-size threshold): the pixels of every tile
 // component are also counted, in LDS, and the count is stored at the
 // component's tile root in the scan's count array.
-template <int TW, int N, bool SIZE>
+// MAPS (the Map Connections of Section III.B.2): a skip edge of offset k
+// exists only when its upper / left end lies on the stride-k map (row and
+// column multiples of k); otherwise every pixel has them.
+template <int TW, int N, bool SIZE, bool MAPS>
 __global__ __launch_bounds__(kLabelThreads) __attribute__((amdgpu_waves_per_eu(N <= 3 ? 8 : 4)))
 void k_tile_label(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
@@ -304,6 +307,12 @@ void k_tile_label(BatchRef ref) {
 
     const uint64_t le = lanes_le(lane);
     const float* at = rs + N * RS + c;                    // at[x * RS + k]: tile row x, column c + k
+    // MAPS: bit k set when this lane's column is a multiple of k
+    [[maybe_unused]] unsigned col_on_map = 0;
+    if constexpr (MAPS) {
+#pragma unroll
+        for (int k = 2; k <= N; ++k) col_on_map |= ((c0 + c) % k == 0 ? 1u : 0u) << k;
+    }
     // 2*cos per lane: c2hk[k-1] for this column and k columns right, c2vl[k-1]
     // for strip row R0 - N + lane and k rows down (0 outside the tile / table)
     float c2hk[N], c2vl[N];
@@ -378,7 +387,9 @@ void k_tile_label(BatchRef ref) {
 #pragma unroll
             for (int k = 2; k <= N; ++k) {
                 const float b = at[r * RS + k];
-                const uint64_t hk = ballot(connected_sq(a, sa, b, b * b, c2hk[k - 1], t2));
+                bool on = true;
+                if constexpr (MAPS) on = (r0 + r) % k == 0 && ((col_on_map >> k) & 1u);
+                const uint64_t hk = ballot(on && connected_sq(a, sa, b, b * b, c2hk[k - 1], t2));
                 run &= h1 >> (k - 1);
                 const uint64_t hneed = hk & ~run & ~((hk & h1 & (h1 >> k)) << 1);
                 if (lane_bit(hneed)) t |= 1u << (N + k - 1);
@@ -397,7 +408,9 @@ void k_tile_label(BatchRef ref) {
             uint64_t chain = v1;
 #pragma unroll
             for (int k = 2; k <= N; ++k) {
-                const uint64_t vk = ballot(connected_sq(wv[k - 1], ws[k - 1], a, sa, c2v(k, j - k + N), t2));
+                bool on = true;                           // MAPS: the upper end, row r - k, on the map
+                if constexpr (MAPS) on = (r0 + r) % k == 0 && ((col_on_map >> k) & 1u);
+                const uint64_t vk = ballot(on && connected_sq(wv[k - 1], ws[k - 1], a, sa, c2v(k, j - k + N), t2));
                 chain &= wv1[k - 2];
                 const uint64_t vneed = vk & ~((vk & h1 & wh1[k - 1]) << 1) & ~chain;
                 if (lane_bit(vneed)) t |= 1u << k;
@@ -735,7 +748,7 @@ __device__ void node_unite(int* npar, const int* keys, int a, int b) {
 // Every crossing edge between two tiles of the scan that is not implied:
 // on_edge(need, root_a, root_b) is called by every lane of a wavefront, with
 // need set on the lanes that hold such an edge.
-template <int TW, int N, typename F>
+template <int TW, int N, bool MAPS, typename F>
 __device__ __forceinline__ void for_crossing_edges(const ScanDesc& d, int lane, int wave, F&& on_edge) {
     constexpr int TH = kTilePx / TW;
     constexpr int kWaves = kMergeThreads / 64;
@@ -794,7 +807,10 @@ __device__ __forceinline__ void for_crossing_edges(const ScanDesc& d, int lane, 
             for (int k = 1; k <= N; ++k) {
                 const int m = j + k - N;                 // target slot
                 if (m < 0) continue;
-                const bool e = connected(vs[j], vt[m], c2h[j][k - 1], t2);
+                bool on = true;                          // MAPS: the left end on the stride-k map
+                if constexpr (MAPS)
+                    if (k >= 2) on = row % k == 0 && (col_end - N + j) % k == 0;
+                const bool e = on && connected(vs[j], vt[m], c2h[j][k - 1], t2);
                 const uint64_t E = ballot(e);
                 const uint64_t V = ballot(us[j] && ut[m]);
                 const bool need = lane_bit(E & ~((E << 1) & V));
@@ -850,7 +866,10 @@ __device__ __forceinline__ void for_crossing_edges(const ScanDesc& d, int lane, 
                 for (int k = 1; k <= N; ++k) {
                     const int m = j + k - N;
                     if (m < 0 || row_end + m >= H) continue;
-                    const bool e = connected(vs[j], vt[m], c2v[j][k - 1], t2);
+                    bool on = true;                      // MAPS: the upper end on the stride-k map
+                    if constexpr (MAPS)
+                        if (k >= 2) on = (row_end - N + j) % k == 0 && col % k == 0;
+                    const bool e = on && connected(vs[j], vt[m], c2v[j][k - 1], t2);
                     const uint64_t E = ballot(e);
                     const uint64_t L = ballot(ls[j] && lt[m]);
                     const bool need = lane_bit(E & ~((E << 1) & L));
@@ -876,7 +895,7 @@ __device__ __forceinline__ void set_slot_final(const ScanDesc& d, int i, int n_c
 // SIZE: after the joins, the pixel count of every border root that is not
 // its component's final root is added to the final root's count, so the
 // count array holds every component's size at its final root.
-template <int TW, int N, bool SIZE>
+template <int TW, int N, bool SIZE, bool MAPS>
 __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
     __shared__ int keys[kNodeCap];             // node -> global root (kNoKey: free)
@@ -914,7 +933,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
             if (r[u] >= 0 && (lane == 0 || prev != r[u]) && node_insert(keys, r[u]) < 0) overflow = 1;
         }
     }
-    for_crossing_edges<TW, N>(d, lane, wave, [&](bool need, int a, int b) {
+    for_crossing_edges<TW, N, MAPS>(d, lane, wave, [&](bool need, int a, int b) {
         if (need && !set_insert(set, a, b)) overflow = 1;
     });
     __syncthreads();
@@ -963,7 +982,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
     }
     if (threadIdx.x == 0) overflow = 0;
     __syncthreads();
-    for_crossing_edges<TW, N>(d, lane, wave, [&](bool need, int a, int b) {
+    for_crossing_edges<TW, N, MAPS>(d, lane, wave, [&](bool need, int a, int b) {
         push_pairs(need, a, b, set, par, &overflow);
     });
     __syncthreads();
@@ -1125,54 +1144,69 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     }
 }
 
-template <int TW, int N, bool SIZE>
+template <int TW, int N, bool SIZE, bool MAPS>
 hipError_t launch_twn(const BatchRef& ref, int n_tiles, int n_scans, hipStream_t stream, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_tile_label<TW, N, SIZE>), dim3(n_tiles), dim3(kLabelThreads), 0, stream, ref);
+    hipLaunchKernelGGL((k_tile_label<TW, N, SIZE, MAPS>), dim3(n_tiles), dim3(kLabelThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan_merge<TW, N, SIZE>), dim3(n_scans), dim3(kMergeThreads), 0, stream, ref);
+    hipLaunchKernelGGL((k_scan_merge<TW, N, SIZE, MAPS>), dim3(n_scans), dim3(kMergeThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_relabel<TW, SIZE>), dim3(n_tiles), dim3(kRelabelThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
-template <int TW, bool SIZE>
+template <int TW, bool SIZE, bool MAPS>
 hipError_t launch_tws(const BatchRef& ref, int skip, int n_tiles, int n_scans, hipStream_t stream,
                       hipEvent_t* ev) {
     switch (skip) {
-        case 1: return launch_twn<TW, 1, SIZE>(ref, n_tiles, n_scans, stream, ev);
-        case 2: return launch_twn<TW, 2, SIZE>(ref, n_tiles, n_scans, stream, ev);
-        case 3: return launch_twn<TW, 3, SIZE>(ref, n_tiles, n_scans, stream, ev);
-        case 4: return launch_twn<TW, 4, SIZE>(ref, n_tiles, n_scans, stream, ev);
-        case 5: return launch_twn<TW, 5, SIZE>(ref, n_tiles, n_scans, stream, ev);
-        case 6: return launch_twn<TW, 6, SIZE>(ref, n_tiles, n_scans, stream, ev);
-        case 7: return launch_twn<TW, 7, SIZE>(ref, n_tiles, n_scans, stream, ev);
-        case 8: return launch_twn<TW, 8, SIZE>(ref, n_tiles, n_scans, stream, ev);
+        case 1: return launch_twn<TW, 1, SIZE, false>(ref, n_tiles, n_scans, stream, ev);   // no skip edges
+        case 2: return launch_twn<TW, 2, SIZE, MAPS>(ref, n_tiles, n_scans, stream, ev);
+        case 3: return launch_twn<TW, 3, SIZE, MAPS>(ref, n_tiles, n_scans, stream, ev);
+        case 4: return launch_twn<TW, 4, SIZE, MAPS>(ref, n_tiles, n_scans, stream, ev);
+        case 5: return launch_twn<TW, 5, SIZE, MAPS>(ref, n_tiles, n_scans, stream, ev);
+        case 6: return launch_twn<TW, 6, SIZE, MAPS>(ref, n_tiles, n_scans, stream, ev);
+        case 7: return launch_twn<TW, 7, SIZE, MAPS>(ref, n_tiles, n_scans, stream, ev);
+        case 8: return launch_twn<TW, 8, SIZE, MAPS>(ref, n_tiles, n_scans, stream, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-// One translation unit per tile width (FLIC_TILE_W), compiled in parallel;
-// without it every width is built here.
-template <int TW>
+// One translation unit per (tile width FLIC_TILE_W, skip-edge mode
+// FLIC_MAPS), compiled in parallel; without them every variant is built here.
+template <int TW, bool MAPS>
 hipError_t launch_cluster_tw(const BatchRef& ref, int skip, bool sized, int n_tiles, int n_scans,
                              hipStream_t stream, hipEvent_t* events) {
-    return sized ? launch_tws<TW, true>(ref, skip, n_tiles, n_scans, stream, events)
-                 : launch_tws<TW, false>(ref, skip, n_tiles, n_scans, stream, events);
+    return sized ? launch_tws<TW, true, MAPS>(ref, skip, n_tiles, n_scans, stream, events)
+                 : launch_tws<TW, false, MAPS>(ref, skip, n_tiles, n_scans, stream, events);
 }
 
+#define FLIC_INSTANTIATE(TW, MAPS) \
+    template hipError_t launch_cluster_tw<TW, MAPS>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*);
+#if !defined(FLIC_MAPS) || FLIC_MAPS == 0
 #if !defined(FLIC_TILE_W) || FLIC_TILE_W == 64
-template hipError_t launch_cluster_tw<64>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*);
+FLIC_INSTANTIATE(64, false)
 #endif
 #if !defined(FLIC_TILE_W) || FLIC_TILE_W == 128
-template hipError_t launch_cluster_tw<128>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*);
+FLIC_INSTANTIATE(128, false)
 #endif
 #if !defined(FLIC_TILE_W) || FLIC_TILE_W == 256
-template hipError_t launch_cluster_tw<256>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*);
+FLIC_INSTANTIATE(256, false)
+#endif
+#endif
+#if !defined(FLIC_MAPS) || FLIC_MAPS == 1
+#if !defined(FLIC_TILE_W) || FLIC_TILE_W == 64
+FLIC_INSTANTIATE(64, true)
+#endif
+#if !defined(FLIC_TILE_W) || FLIC_TILE_W == 128
+FLIC_INSTANTIATE(128, true)
+#endif
+#if !defined(FLIC_TILE_W) || FLIC_TILE_W == 256
+FLIC_INSTANTIATE(256, true)
+#endif
 #endif
 
 }  // namespace flic

@@ -35,7 +35,7 @@ class _Scan(ctypes.Structure):
     _fields_ = [("range_img", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
                 ("tables", _Tables), ("threshold", ctypes.c_float),
                 ("skip_depth", ctypes.c_int32), ("labels_out", ctypes.c_void_p),
-                ("min_points", ctypes.c_int32)]
+                ("min_points", ctypes.c_int32), ("map_connections", ctypes.c_int32)]
 
 
 class _GroundTables(ctypes.Structure):
@@ -174,6 +174,7 @@ class DeviceScan:
     skip_depth: int
     labels: "object" = None
     min_points: int = 0
+    map_connections: int = 0
 
     def validate(self) -> None:
         import torch
@@ -191,7 +192,7 @@ class DeviceScan:
         return _Scan(self.range_img.data_ptr(), H, W,
                      _Tables(self.cos_v.data_ptr(), self.cos_h.data_ptr()),
                      float(self.threshold), int(self.skip_depth), self.labels.data_ptr(),
-                     int(self.min_points))
+                     int(self.min_points), int(self.map_connections))
 
 
 class Context:
@@ -267,7 +268,7 @@ class Context:
 
     def cluster_async(self, scan: DeviceScan, stream=None):
         scan.validate()
-        if scan.min_points:                 # the size threshold is a flic_scan field
+        if scan.min_points or scan.map_connections:    # flic_scan fields only
             return self.cluster_batched([scan], stream)[0]
         H, W = scan.range_img.shape
         t = _Tables(scan.cos_v.data_ptr(), scan.cos_h.data_ptr())
@@ -437,12 +438,13 @@ def ground_remove(range_img, tables: DeviceGroundTables, out=None, mask=None, st
     return out, mask
 
 
-def to_device(scan, device="cuda", min_points: int = 0) -> DeviceScan:
+def to_device(scan, device="cuda", min_points: int = 0, map_connections: int = 0) -> DeviceScan:
     """Copy a host scan (synth.Scan) to device tensors."""
     import torch
     d = DeviceScan(torch.from_numpy(scan.range_img).to(device),
                    torch.from_numpy(scan.cos_v).to(device),
                    torch.from_numpy(scan.cos_h).to(device),
-                   scan.threshold, scan.skip_depth, min_points=min_points)
+                   scan.threshold, scan.skip_depth, min_points=min_points,
+                   map_connections=map_connections)
     d.validate()          # allocates the labels tensor
     return d
