@@ -8,6 +8,9 @@ batched launches of 64 scans (50.3 Mpix per step).  Each launch is a hipGraph
 plan; launches rotate over --sets disjoint copies of the inputs and outputs so
 that no launch finds its data in the 256 MB last-level cache.
 
+With --map-connections the skip edges come from the stride-k maps of Section
+III.B.2 (the paper's own Map Connections) instead of every pixel.
+
 With --min-points M the same step also applies the cluster-size threshold of
 Section III.B.1 (components with fewer than M points labelled -1; the paper
 uses 100): the counting variants of the three kernels run instead.
@@ -32,6 +35,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PROFILE_RECORD = os.path.join(ROOT, "profiles", "flic_passes_large_batch_64x128x2048.txt")
 PROFILE_RECORD_SIZED = os.path.join(ROOT, "profiles", "flic_passes_large_batch_64x128x2048_min100.txt")
+PROFILE_RECORD_MAPS = os.path.join(ROOT, "profiles", "flic_passes_large_batch_64x128x2048_maps.txt")
 # vector-instruction issue peak: 256 CUs x one wave64 VALU instruction per CU
 # per cycle (4 SIMD16 units, 4 cycles each) x 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 2.4e9
@@ -174,9 +178,12 @@ def main() -> int:
                     help="also run one plain 128 MiB device copy (reference for byte counters)")
     ap.add_argument("--min-points", type=int, default=0,
                     help="cluster-size threshold of Section III.B.1 (0 = none; the paper uses 100)")
+    ap.add_argument("--map-connections", action="store_true",
+                    help="skip edges from the stride-k maps of Section III.B.2")
     args = ap.parse_args()
     MP = max(0, args.min_points)
-    record_path = PROFILE_RECORD_SIZED if MP == 100 else (PROFILE_RECORD if MP == 0 else "")
+    MC = 1 if args.map_connections else 0
+    record_path = {(0, 0): PROFILE_RECORD, (100, 0): PROFILE_RECORD_SIZED, (0, 1): PROFILE_RECORD_MAPS}.get((MP, MC), "")
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -208,7 +215,7 @@ def main() -> int:
               for _ in range(S)]
 
     def scans_for(s, ti):
-        return [flic.DeviceScan(ranges[s][i], cos_v[i], cos_h[i], THRESHOLDS[ti], SKIP, labels[s][ti][i], MP)
+        return [flic.DeviceScan(ranges[s][i], cos_v[i], cos_h[i], THRESHOLDS[ti], SKIP, labels[s][ti][i], MP, MC)
                 for i in range(N_SCANS)]
 
     from paper_2003_00575_amd import autotune
@@ -318,7 +325,7 @@ def main() -> int:
 
     # ---- latency of the plain per-scan path (64 x 2048 scan) ----------------
     c1 = synth.single_scan(1)
-    d1 = flic.to_device(c1, dev, min_points=MP)
+    d1 = flic.to_device(c1, dev, min_points=MP, map_connections=MC)
     for _ in range(20):
         ctx.cluster_async(d1, stream)
     torch.cuda.synchronize()
@@ -355,14 +362,15 @@ def main() -> int:
         done_px, n_calls, t = 0, 0, time.perf_counter()
         while time.perf_counter() - t < args.cpu_seconds:
             s = host[n_calls % N_SCANS]
-            oracle.cluster(s.range_img, s.cos_v, s.cos_h, THRESHOLDS[n_calls % 3], SKIP, MP)
+            oracle.cluster(s.range_img, s.cos_v, s.cos_h, THRESHOLDS[n_calls % 3], SKIP, MP, MC)
             done_px += H * W
             n_calls += 1
         el = time.perf_counter() - t
         cpu = {"value": round(done_px / el / 1e9, 6), "unit": "Gpix/s", "cores": 1, "kind": "oracle",
                "sample": f"{n_calls} oracle calls on the {H}x{W} scans of this batch "
                          f"(thresholds cycling 0.3/0.5/1.0, skip 3"
-                         f"{f', min {MP} points' if MP else ''}), {el:.1f} s on one host core"}
+                         f"{f', min {MP} points' if MP else ''}{', map connections' if MC else ''}), "
+                         f"{el:.1f} s on one host core"}
 
     out = {
         "metric": "range pixels/sec (Gpix/s) batched + p50/p99 scan latency, labels bit-exact",
@@ -382,9 +390,10 @@ def main() -> int:
                                f"{'one stream each' if args.streams > 1 else 'one stream'}), "
                                f"skip depth {SKIP}, "
                                f"{f'cluster-size threshold {MP} points, ' if MP else ''}"
+                               f"{'skip edges from the stride-k maps (Section III.B.2), ' if MC else ''}"
                                f"hipGraph plans, {S} rotating buffer sets",
                    "global_batch": N_SCANS * len(THRESHOLDS), "pixels_per_step": px_per_step,
-                   "min_points": MP,
+                   "min_points": MP, "map_connections": MC,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -406,7 +415,8 @@ def main() -> int:
                               "scans_s": round(N_SCANS * len(THRESHOLDS) * reps / (single_ms * 1e-3), 1)},
         "batched_scans_s": round(N_SCANS * len(THRESHOLDS) * args.steps / (gpu_ms * 1e-3), 1),
         "latency_ms": {"workload": "single 64x2048 scan, T=0.5, skip 3, " + (
-                           f"min {MP} points, flic_cluster_batched (n=1)" if MP else "flic_cluster_async"),
+                           (f"min {MP} points, " if MP else "") + ("map connections, " if MC else "") +
+                           "flic_cluster_batched (n=1)" if (MP or MC) else "flic_cluster_async"),
                        "reps": args.latency_reps,
                        "host_p50": round(percentile(lat_host, 0.5), 4),
                        "host_p99": round(percentile(lat_host, 0.99), 4),
