@@ -16,9 +16,10 @@ Rules, as the evaluation states them:
 
     python -m paper_2003_00575_amd.quality [--scans K]
 
-clusters synthetic scenes on the GPU over a grid of thresholds and skip
-depths, with the generator's ground removed and with the ground extraction
-of Section III.A, and prints mean IoU and P_mu for each setting.
+clusters synthetic scenes on the GPU over a grid of thresholds, skip depths
+and skip-edge modes (dense, or the Map Connections of Section III.B.2), with
+the generator's ground removed and with the ground extraction of Section
+III.A, and prints mean IoU and P_mu for each setting.
 """
 from __future__ import annotations
 
@@ -81,7 +82,7 @@ def summarize(ious: Iterable[float]) -> Dict[str, float]:
     return out
 
 
-def _sweep(n_scans: int, thresholds: List[float], depths: List[int]) -> List[dict]:
+def _sweep(n_scans: int, thresholds: List[float], depths: List[int], modes=(0,)) -> List[dict]:
     import torch
     from paper_2003_00575_amd import flic, synth
     scans = [synth.large_batch_scan(100 + i, 0.5) for i in range(n_scans)]
@@ -94,12 +95,12 @@ def _sweep(n_scans: int, thresholds: List[float], depths: List[int]) -> List[dic
     ctx = flic.Context(0)
     rows = []
     for ground, imgs in (("ground truth", gt_removed), ("Section III.A", ours)):
-        for N in depths:
+        for N, mc in [(N, mc) for N in depths for mc in modes if not (mc and N == 1)]:
             tabs = [synth.make_tables(s.phi, s.W, N) for s in scans]
             cv = [torch.from_numpy(t[0]).to(dev) for t in tabs]
             ch = [torch.from_numpy(t[1]).to(dev) for t in tabs]
             for T in thresholds:
-                devs = [flic.DeviceScan(imgs[i], cv[i], ch[i], T, N) for i in range(n_scans)]
+                devs = [flic.DeviceScan(imgs[i], cv[i], ch[i], T, N, None, 0, mc) for i in range(n_scans)]
                 ctx.cluster_batched(devs)
                 torch.cuda.synchronize()
                 ious = []
@@ -107,9 +108,9 @@ def _sweep(n_scans: int, thresholds: List[float], depths: List[int]) -> List[dic
                     lab = devs[i].labels.cpu().numpy()
                     measured = s.range_img > 0
                     ious.extend(instance_ious(lab, s.object_id, measured).values())
-                row = {"ground": ground, "N": N, "T": T, **summarize(ious)}
+                row = {"ground": ground, "N": N, "maps": mc, "T": T, **summarize(ious)}
                 rows.append(row)
-                print(f"ground {ground:14s} N={N} T={T:.2f}: {row['instances']} instances, "
+                print(f"ground {ground:14s} N={N} {'maps ' if mc else 'dense'} T={T:.2f}: {row['instances']} instances, "
                       f"IoU {row['iou_mean']:.3f}, P_mu {row['P_mu']:.3f}, P_0.50 {row['P_0.50']:.3f}, "
                       f"P_0.75 {row['P_0.75']:.3f}, P_0.95 {row['P_0.95']:.3f}", flush=True)
     return rows
@@ -120,10 +121,11 @@ def main(argv=None) -> int:
     ap.add_argument("--scans", type=int, default=16)
     ap.add_argument("--thresholds", default="0.3,0.5,0.8,1.0")
     ap.add_argument("--depths", default="1,2,3,5")
+    ap.add_argument("--modes", default="0,1", help="skip-edge modes: 0 dense, 1 Map Connections")
     ap.add_argument("--json", default="")
     args = ap.parse_args(argv)
     rows = _sweep(args.scans, [float(x) for x in args.thresholds.split(",")],
-                  [int(x) for x in args.depths.split(",")])
+                  [int(x) for x in args.depths.split(",")], [int(x) for x in args.modes.split(",")])
     if args.json:
         with open(args.json, "w") as f:
             json.dump(rows, f)
