@@ -6,8 +6,9 @@
 //
 //   k_tile_label   one workgroup per tile.
 //     load   coalesced (float4 where aligned) copy of the tile's ranges into
-//            LDS, missing pixels replaced by NaN; the tile's slices of the
-//            angle tables staged in LDS as 2*cos.
+//            LDS, missing pixels replaced by NaN; the angle-table values each
+//            lane needs loaded into registers as 2*cos (a lane's column, and
+//            one strip row per lane, read across lanes).
 //     edges  per 64-pixel row chunk (one wavefront, lane = column, 8 rows
 //            walked top-down) the edge test of Eq. (4) against the pixel k
 //            columns right and k rows up, k = 1..N, each turned into a 64-bit
@@ -37,10 +38,17 @@
 //            roots to final roots in LDS and expands the run roots into the
 //            final labels, one coalesced store per pixel.
 //
+// Variants (template flags, so the plain path compiles without them): SIZE
+// also counts each component's pixels (tile pass in LDS, merge at final
+// roots) and drops components below the scan's min_points in the relabel
+// (Section III.B.1); MAPS keeps a k-step skip edge only when its upper / left
+// end lies on the stride-k map (the Map Connections of Section III.B.2).
+//
 // The edge test is bit-identical to a scalar binary32 evaluation: contraction
-// is off for the whole file (the build checks the ISA has no fused
-// multiply-add); a missing pixel is NaN so any distance involving it is NaN
-// and the ordered compare rejects it.
+// is off for the whole file (-ffp-contract=off and the pragma below; the
+// kernels' gfx950 assembly holds no v_fma, v_mad or v_pk_*_f32); a missing
+// pixel is NaN so any distance involving it is NaN and the ordered compare
+// rejects it.
 
 #include "flic_internal.h"
 
