@@ -105,7 +105,9 @@ void flic_ctx_destroy(flic_ctx* ctx);
 
 /* Cluster one scan (all pointers device pointers, see flic_scan for the
  * layout) and block until the labels are written.  Uses a per-thread default
- * context on the current HIP device and the null stream.                   */
+ * context on the current HIP device and the null stream.  The single-scan
+ * entry points use dense skip edges and no size threshold (map_connections
+ * = 0, min_points = 0); flic_cluster_batched with n = 1 takes the others.  */
 flic_status flic_cluster(const float* range_img, int32_t H, int32_t W,
                          const flic_alpha_tables* alpha_tables,
                          float threshold, int32_t skip_depth,
