@@ -50,10 +50,11 @@ __global__ __launch_bounds__(kGroundThreads) void k_ground(GroundArgs a) {
     // XCD with its own L2.  Each XCD takes one contiguous eighth of the
     // work, in order, so the row above and below a workgroup's rows was
     // just read into the same L2 by its neighbour in the walk.
-    const unsigned total = gridDim.x * gridDim.y;
-    const unsigned p = blockIdx.y * gridDim.x + blockIdx.x;
-    const unsigned work = (total % 8u) == 0 ? (p % 8u) * (total / 8u) + p / 8u : p;
-    const unsigned sid = work / gridDim.x, blk = work % gridDim.x;
+    // (64-bit: thin scans can make the grid larger than 2^32 blocks)
+    const uint64_t total = (uint64_t)gridDim.x * gridDim.y;
+    const uint64_t p = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const uint64_t work = (total % 8u) == 0 ? (p % 8u) * (total / 8u) + p / 8u : p;
+    const unsigned sid = (unsigned)(work / gridDim.x), blk = (unsigned)(work % gridDim.x);
     const int bx = blk % col_blocks, by = blk / col_blocks;
     const int c = (bx * kGroundThreads + threadIdx.x) * V;
     const int r0 = by * kRows;
