@@ -4,7 +4,8 @@ scans of every shape class with their own tables, ragged sizes (rows not a
 multiple of the 16-row lane walk, columns not a multiple of the 256-column
 workgroup), special values, noise-free ground and vertical faces, the
 first-row and missing-above rules, argument errors, and ground removal
-followed by clustering (with and without the size threshold)."""
+followed by clustering (the paper's whole pipeline: ground extraction, Map
+Connections, the 100-point threshold)."""
 import math
 
 import numpy as np
@@ -121,8 +122,8 @@ def test_argument_errors(flic):
     assert out.shape == (0, s.H, s.W)
 
 
-@pytest.mark.parametrize("m", [0, 100])
-def test_ground_then_cluster(flic, m):
+@pytest.mark.parametrize("m, mc", [(0, 0), (100, 0), (100, 1)])
+def test_ground_then_cluster(flic, m, mc):
     scans = [synth.large_batch_scan(i, 0.5) for i in range(8)]
     g = synth.ground_tables(scans[0].phi)
     imgs = np.stack([s.range_img for s in scans])
@@ -132,14 +133,14 @@ def test_ground_then_cluster(flic, m):
     devs = []
     for i, s in enumerate(scans):
         devs.append(flic.DeviceScan(out[i], torch.from_numpy(s.cos_v).cuda(), torch.from_numpy(s.cos_h).cuda(),
-                                    s.threshold, s.skip_depth, None, m))
+                                    s.threshold, s.skip_depth, None, m, mc))
     ctx.cluster_batched(devs)
     torch.cuda.synchronize()
     for i, s in enumerate(scans):
         _, wo = oracle.ground(s.range_img, g)
-        want = oracle.cluster(wo, s.cos_v, s.cos_h, s.threshold, s.skip_depth, m)
+        want = oracle.cluster(wo, s.cos_v, s.cos_h, s.threshold, s.skip_depth, m, mc)
         got = devs[i].labels.cpu().numpy()
         assert np.array_equal(got, want), f"scan {i}: {(got != want).sum()} labels differ"
-        if m == 0:
+        if m == 0 and mc == 0:
             # the ground no longer joins objects: more components than before
             assert len(np.unique(want)) > len(np.unique(oracle.cluster_scan(s)))
