@@ -104,8 +104,9 @@ flic_status flic_ctx_create(flic_ctx** out, int device, size_t hbm_budget_bytes)
 void flic_ctx_destroy(flic_ctx* ctx);
 
 /* Cluster one scan (all pointers device pointers, see flic_scan for the
- * layout) and block until the labels are written.  Uses a per-thread default
- * context on the current HIP device and the null stream.  The single-scan
+ * layout) and block until the labels are written.  Uses one default context
+ * per HIP device, shared by all host threads (their launches are serialised,
+ * their waits are not), on the current device and the null stream.  The single-scan
  * entry points use dense skip edges and no size threshold (map_connections
  * = 0, min_points = 0); flic_cluster_batched with n = 1 takes the others.  */
 flic_status flic_cluster(const float* range_img, int32_t H, int32_t W,
@@ -143,7 +144,9 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n,
  * positive.  Pointers,
  * thresholds and positive min_points values may differ: changed
  * descriptors are uploaded before the graph launch.  FLIC_EINVAL on a
- * shape mismatch.                                                          */
+ * shape mismatch.  A plan owns one scratch buffer, so its launches run one
+ * after the other: a launch on a different stream from the previous one
+ * first waits (on the device, without blocking the host) for that launch.  */
 flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
                              void* hip_stream);
 

@@ -527,14 +527,18 @@ flic_status flic_cluster(const float* range_img, int32_t H, int32_t W,
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(FLIC_EINVAL, "device %d", dev);
-    std::lock_guard<std::mutex> lk(g_default_mu);
-    if (!g_default_ctx[dev]) {
-        st = flic_ctx_create(&g_default_ctx[dev], dev, 0);
+    {
+        // one shared context per device: the launch is serialised, the wait
+        // for its completion is not
+        std::lock_guard<std::mutex> lk(g_default_mu);
+        if (!g_default_ctx[dev]) {
+            st = flic_ctx_create(&g_default_ctx[dev], dev, 0);
+            if (st != FLIC_OK) return st;
+        }
+        st = flic_cluster_async(g_default_ctx[dev], range_img, H, W, alpha_tables, threshold,
+                                skip_depth, labels_out, nullptr);
         if (st != FLIC_OK) return st;
     }
-    st = flic_cluster_async(g_default_ctx[dev], range_img, H, W, alpha_tables, threshold,
-                            skip_depth, labels_out, nullptr);
-    if (st != FLIC_OK) return st;
     HIP_TRY(hipStreamSynchronize(nullptr));
     return FLIC_OK;
 }
@@ -675,6 +679,9 @@ flic_status flic_plan_launch(flic_plan* plan, const flic_scan* scans, int32_t n,
                                hipMemcpyHostToDevice, stream));
         plan->shapes.assign(scans, scans + n);
     }
+    // Launches of one plan share its scratch: a launch on another stream
+    // waits for the previous one on the device (a no-op on the same stream).
+    if (plan->launched) HIP_TRY(hipStreamWaitEvent(stream, plan->done, 0));
     HIP_TRY(hipGraphLaunch(plan->exec, stream));
     HIP_TRY(hipEventRecord(plan->done, stream));
     plan->launched = true;

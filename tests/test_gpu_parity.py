@@ -227,3 +227,26 @@ def test_merge_pair_set_overflow(flic):
     torch.cuda.synchronize()
     assert_same(d.labels.cpu().numpy(), want, "pair-set overflow, plan")
     plan.close()
+
+
+def test_plan_relaunch_on_two_streams(flic):
+    """A plan's launches share its scratch: back-to-back launches of an
+    unchanged plan on two streams must run one after the other, so every
+    launch writes the oracle's labels."""
+    scans = [synth.large_batch_scan(i, 0.5) for i in range(8)]
+    want = [oracle.cluster_scan(s) for s in scans]
+    ctx = flic.Context(0)
+    devs = [flic.to_device(s) for s in scans]
+    plan = ctx.plan(devs)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for rep in range(6):
+        for d in devs:
+            d.labels.fill_(-9)
+        torch.cuda.synchronize()
+        for k in range(8):
+            plan.relaunch(streams[k % 2])
+        torch.cuda.synchronize()
+        for i, d in enumerate(devs):
+            assert_same(d.labels.cpu().numpy(), want[i], f"rep {rep} scan {i}")
+    plan.close()
