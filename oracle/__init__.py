@@ -14,7 +14,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "flic_oracle.c")
-_LIB = os.path.join(_HERE, "libflic_oracle.so")
+# FLIC_ORACLE_LIB points the wrapper at another build of the same source (the
+# sanitizer tests load an AddressSanitizer / UBSan build this way).
+_LIB = os.environ.get("FLIC_ORACLE_LIB") or os.path.join(_HERE, "libflic_oracle.so")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared"]
 
 _lib: Optional[ctypes.CDLL] = None

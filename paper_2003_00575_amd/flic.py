@@ -12,7 +12,9 @@ import os
 from typing import List, Optional, Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libflic.so")
+# FLIC_LIB selects another build of the library (the host-sanitizer test
+# loads one whose host code is built with AddressSanitizer / UBSan).
+LIB_PATH = os.environ.get("FLIC_LIB") or os.path.join(HERE, "libflic.so")
 
 FLIC_OK = 0
 FLIC_EINVAL = -1

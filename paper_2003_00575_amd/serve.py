@@ -113,6 +113,11 @@ class ServingCore:
       launch(stream, [(sensor, slot)]) -> token enqueue copies + one launch
       done(token) -> bool
       scratch_bytes(max_batch_px) -> int        library scratch for a batch
+    and may provide
+      ring_bytes(max_batch, spec) -> int        exact device bytes of the
+                                                library's launch ring once
+                                                reserved for max_batch scans of
+                                                the largest shape (preferred)
     """
 
     def __init__(self, backend, hbm_budget: int, n_streams: int = 3, max_batch: int = 64,
@@ -143,9 +148,11 @@ class ServingCore:
         # the library's launch ring: one batch of the largest shapes per stream
         if not self.specs:
             return 0
-        biggest = max(s.H * s.W for s in self.specs.values())
+        biggest = max(self.specs.values(), key=lambda s: s.H * s.W)
+        if hasattr(self.b, "ring_bytes"):
+            return self.b.ring_bytes(self.max_batch, biggest)
         slots = getattr(self.b, "ring_slots", self.n_streams)
-        return self.b.scratch_bytes(self.max_batch * biggest) * slots
+        return self.b.scratch_bytes(self.max_batch * biggest.H * biggest.W) * slots
 
     def add_sensor(self, spec: SensorSpec) -> None:
         need = self.resident_bytes(spec)
@@ -259,6 +266,15 @@ class ServingCore:
 # GPU backend
 # ---------------------------------------------------------------------------
 
+def _ring_cap(need: int) -> int:
+    """Size of a launch-slot buffer holding `need` bytes: the library grows
+    each slot buffer to the next power of two, at least 4 KiB."""
+    cap = 4096
+    while cap < need:
+        cap *= 2
+    return cap
+
+
 class GpuBackend:
     """Device side of the serving loop: resident tables and frame slots,
     copies on the launch streams, batched (or per-scan) launches."""
@@ -286,17 +302,33 @@ class GpuBackend:
         return cv.nbytes + ch.nbytes
 
     def scratch_bytes(self, px: int) -> int:
-        return px * 5                      # parent array + masks + border arrays, generous
+        raise NotImplementedError("GpuBackend sizes the launch ring with ring_bytes")
+
+    def _ring_request(self, max_batch: int, spec: SensorSpec) -> Tuple[int, int]:
+        """Descriptor and scratch bytes each launch slot is sized for: the
+        library's figures for one scan of this shape, times the batch size
+        (the block map and scratch grow with every scan of a batch)."""
+        flic = self.flic
+        # never-dereferenced, non-overlapping addresses: flic_batch_bytes only
+        # validates them
+        st = flic._Scan(1 << 40, spec.H, spec.W, flic._Tables(3 << 40, 4 << 40), float(spec.threshold),
+                        int(spec.skip_depth), 2 << 40)
+        desc, scratch = self.ctx.batch_bytes([st])
+        n = max(1, max_batch)
+        return desc * n, scratch * n
+
+    def ring_bytes(self, max_batch: int, spec: SensorSpec) -> int:
+        """Device bytes of the library's launch ring after reserve(): every
+        slot's descriptor and scratch buffer, each rounded up to a power of
+        two of at least 4 KiB as flic_ctx_reserve sizes them."""
+        desc, scratch = self._ring_request(max_batch, spec)
+        return self.ring_slots * (_ring_cap(desc) + _ring_cap(scratch))
 
     def reserve(self, max_batch: int) -> None:
         """Size the library's launch slots for the largest possible batch now,
         so no launch allocates (or frees, which synchronises the device)."""
         biggest = max(self.specs.values(), key=lambda s: s.H * s.W)
-        st = self.slots[(biggest.sensor, 0)]["struct"]
-        desc, scratch = self.ctx.batch_bytes([st])
-        n = max(1, max_batch)
-        # descriptors + block map grow with the tile count; scratch with pixels
-        self.ctx.reserve(desc * n, scratch * n)
+        self.ctx.reserve(*self._ring_request(max_batch, biggest))
 
     def register(self, spec: SensorSpec, n_slots: int) -> None:
         torch = self.torch
@@ -380,13 +412,16 @@ def serve_once(specs, frames, tables, rates, seconds: float, speedup: float, bat
     import torch
     from . import flic
     from . import autotune
-    ctx = flic.Context(0)
+    ctx = flic.Context(0, hbm_budget_bytes=budget)       # the library enforces the cap on its own buffers
     autotune.apply_default(ctx)
     be = GpuBackend(ctx, frames, tables, n_streams, batched=batched, keep_labels=keep_labels)
     core = ServingCore(be, budget, n_streams=n_streams, max_batch=max_batch if batched else 1)
     for sp in specs:
         core.add_sensor(sp)
     be.reserve(max_batch if batched else 1)
+    if ctx.bytes_in_use() > core.scratch_reserve():
+        raise BudgetError(f"the library holds {ctx.bytes_in_use()} bytes, admission counted "
+                          f"{core.scratch_reserve()}")
     # warm the launch paths before the clock starts
     warm = [(0.0, sp.sensor, 0) for sp in specs]
     core.run(warm)

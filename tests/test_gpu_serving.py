@@ -62,14 +62,17 @@ def test_budget_admission_on_device(flic):
     be = serve.GpuBackend(ctx, frames, tables, n_streams=2)
     probe = serve.ServingCore(be, 1 << 40, n_streams=2, max_batch=4)
     two = sum(probe.resident_bytes(s) for s in specs[:2])
-    biggest = max(s.H * s.W for s in specs[:2])
-    core = serve.ServingCore(be, two + be.scratch_bytes(4 * biggest) * be.ring_slots, n_streams=2,
-                             max_batch=4)
+    biggest = max(specs[:2], key=lambda s: s.H * s.W)
+    core = serve.ServingCore(be, two + be.ring_bytes(4, biggest), n_streams=2, max_batch=4)
     core.add_sensor(specs[0])
     core.add_sensor(specs[1])
     with pytest.raises(serve.BudgetError):
         core.add_sensor(specs[2])             # a bigger sensor no longer fits
     assert sorted(core.specs) == [0, 1]
+    # what admission charged for the library's launch ring is what it holds
+    be.reserve(4)
+    assert ctx.bytes_in_use() == core.scratch_reserve()
+    assert core.reserved + core.scratch_reserve() <= core.budget
 
 
 def test_autotune_rules_keep_labels(flic, tmp_path):
