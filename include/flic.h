@@ -124,6 +124,25 @@ flic_status flic_cluster_async(flic_ctx* ctx, const float* range_img,
                                float threshold, int32_t skip_depth,
                                int32_t* labels_out, void* hip_stream);
 
+/* Allocation-free form of flic_cluster_async, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): no context, and no allocation of
+ * any kind.  Its scratch is a fixed device array of 16 MiB per device
+ * (FLIC_NOALLOC_SCRATCH_BYTES), reserved by the library until the process
+ * ends; a scan whose scratch exceeds it (tile pass masks and run roots,
+ * border slots and a 4-byte-per-pixel parent array: a 128 x 4096 scan at
+ * skip depth 8 needs about 3.4 MiB) returns FLIC_EINVAL with nothing
+ * enqueued.  Enqueues on `hip_stream` (null: the null stream) on the current
+ * device and returns at once.  All calls on one device share that array, so
+ * calls whose work overlaps on the device race and give wrong labels: order
+ * them on one stream, or wait for one before starting the next.  Same
+ * arguments, validation and labels as flic_cluster_async.                   */
+#define FLIC_NOALLOC_SCRATCH_BYTES (16u << 20)
+flic_status flic_cluster_noalloc(const float* range_img, int32_t H, int32_t W,
+                                 const flic_alpha_tables* alpha_tables,
+                                 float threshold, int32_t skip_depth,
+                                 int32_t* labels_out, void* hip_stream);
+
 /* Cluster n independent scans of any shapes, thresholds and skip depths in
  * one stream-ordered sequence of launches (no per-scan launches).  `scans`
  * is a host array read during the call.  Each scan's labels are identical to

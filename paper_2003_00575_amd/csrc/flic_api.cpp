@@ -19,6 +19,8 @@
 
 using flic::ScanDesc;
 
+static_assert(FLIC_NOALLOC_SCRATCH_BYTES == flic::kNoAllocScratchBytes, "header and library agree");
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -540,6 +542,29 @@ flic_status flic_cluster(const float* range_img, int32_t H, int32_t W,
         if (st != FLIC_OK) return st;
     }
     HIP_TRY(hipStreamSynchronize(nullptr));
+    return FLIC_OK;
+}
+
+flic_status flic_cluster_noalloc(const float* range_img, int32_t H, int32_t W,
+                                 const flic_alpha_tables* alpha_tables, float threshold,
+                                 int32_t skip_depth, int32_t* labels_out, void* hip_stream) {
+    flic_status st = check_scan(range_img, H, W, alpha_tables, threshold, skip_depth, labels_out, 0);
+    if (st != FLIC_OK) return st;
+    const int tw = choose_tile_w(nullptr, H, W, skip_depth);
+    const size_t need = flic::scratch_layout(H, W, skip_depth, tw, false).total;
+    if (need > flic::kNoAllocScratchBytes)
+        return fail(FLIC_EINVAL, "a %dx%d scan with skip_depth %d needs %zu bytes of scratch; "
+                    "flic_cluster_noalloc holds %zu", H, W, skip_depth, need, flic::kNoAllocScratchBytes);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= flic::kMaxDevices) return fail(FLIC_EINVAL, "device %d", dev);
+    void* scratch = nullptr;
+    HIP_TRY(flic::noalloc_scratch(dev, &scratch));
+    const flic_scan s{range_img, H, W, *alpha_tables, threshold, skip_depth, labels_out, 0, 0};
+    flic::BatchRef ref{};
+    ref.one = make_desc(s, tw, 0, static_cast<char*>(scratch));
+    HIP_TRY(launch_cluster(ref, tw, skip_depth, false, false, ref.one.tiles_x * ref.one.tiles_y, 1,
+                           static_cast<hipStream_t>(hip_stream)));
     return FLIC_OK;
 }
 

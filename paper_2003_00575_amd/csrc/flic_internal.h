@@ -136,4 +136,12 @@ struct GroundArgs {
 
 hipError_t launch_ground(const GroundArgs& a, int n_scans, hipStream_t stream);
 
+// Scratch of the allocation-free entry point: a file-scope device array of
+// kNoAllocScratchBytes per device.  noalloc_scratch returns its device
+// address on `device`, which must be the current device (looked up once per
+// device, then cached).
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, void** out);
+
 }  // namespace flic

@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
     L.flic_cluster.restype = i32
     L.flic_cluster_async.argtypes = [vp, vp, i32, i32, ctypes.POINTER(_Tables), f32, i32, vp, vp]
     L.flic_cluster_async.restype = i32
+    L.flic_cluster_noalloc.argtypes = [vp, i32, i32, ctypes.POINTER(_Tables), f32, i32, vp, vp]
+    L.flic_cluster_noalloc.restype = i32
     L.flic_cluster_batched.argtypes = [vp, ctypes.POINTER(_Scan), i32, vp]
     L.flic_cluster_batched.restype = i32
     L.flic_plan_create.argtypes = [vp, ctypes.POINTER(_Scan), i32, ctypes.POINTER(vp)]
@@ -127,6 +129,14 @@ def cluster_async_raw(ctx: int, range_ptr: int, H: int, W: int, cos_v_ptr: int, 
     t = _Tables(cos_v_ptr, cos_h_ptr)
     return lib().flic_cluster_async(ctx, range_ptr, H, W, ctypes.byref(t), threshold,
                                     skip_depth, labels_ptr, stream)
+
+
+def cluster_noalloc_raw(range_ptr: int, H: int, W: int, cos_v_ptr: int, cos_h_ptr: int,
+                        threshold: float, skip_depth: int, labels_ptr: int, stream: int) -> int:
+    """flic_cluster_noalloc with raw device addresses; returns the status code."""
+    t = _Tables(cos_v_ptr, cos_h_ptr)
+    return lib().flic_cluster_noalloc(range_ptr, H, W, ctypes.byref(t), threshold, skip_depth,
+                                      labels_ptr, stream)
 
 
 def batched_raw(ctx: int, scans: Sequence[tuple], stream: int) -> int:
@@ -370,6 +380,19 @@ def cluster_sync(range_img, cos_v, cos_h, threshold: float, skip_depth: int, out
     H, W = range_img.shape
     _check(cluster_raw(range_img.data_ptr(), H, W, cos_v.data_ptr(), cos_h.data_ptr(),
                        float(threshold), int(skip_depth), s.labels.data_ptr()))
+    return s.labels
+
+
+def cluster_noalloc(range_img, cos_v, cos_h, threshold: float, skip_depth: int, out=None, stream=None):
+    """flic_cluster_noalloc: labels int32 [H, W] of one scan, enqueued on
+    `stream` (default: the current torch stream) with the library's fixed
+    device scratch (no allocation; calls overlapping on one device race)."""
+    s = DeviceScan(range_img, cos_v, cos_h, threshold, skip_depth, out)
+    s.validate()
+    H, W = range_img.shape
+    _check(cluster_noalloc_raw(range_img.data_ptr(), H, W, cos_v.data_ptr(), cos_h.data_ptr(),
+                               float(threshold), int(skip_depth), s.labels.data_ptr(),
+                               _stream_handle(stream)))
     return s.labels
 
 

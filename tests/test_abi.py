@@ -107,3 +107,11 @@ def test_ground_tables_struct_layout_matches_header(tmp_path):
 
 def test_ground_remove_rejects_null_ctx(L):
     assert L.flic_ground_remove(None, None, 1, 4, 4, None, None, None, None) == flic.FLIC_EINVAL
+
+
+def test_noalloc_rejects_before_any_hip_call(L):
+    # argument errors as for flic_cluster, and a scan beyond the fixed scratch
+    assert flic.cluster_noalloc_raw(0, 4, 64, CV, CH, 0.5, 3, LBL, 0) == flic.FLIC_EINVAL
+    assert flic.cluster_noalloc_raw(R, 4, 64, CV, CH, 0.5, 9, LBL, 0) == flic.FLIC_EINVAL
+    assert flic.cluster_noalloc_raw(R, 1024, 4096, CV, CH, 0.5, 3, LBL, 0) == flic.FLIC_EINVAL
+    assert "scratch" in flic.last_error()
