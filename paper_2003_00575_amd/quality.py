@@ -82,19 +82,44 @@ def summarize(ious: Iterable[float]) -> Dict[str, float]:
     return out
 
 
-def _sweep(n_scans: int, thresholds: List[float], depths: List[int], modes=(0,)) -> List[dict]:
+def literal_first_channel(range_img: np.ndarray, ground: np.ndarray) -> np.ndarray:
+    """The ground mask under the literal reading of Section III.A's first-
+    channel rule, from the mask of the extended reading: only row 0 takes the
+    pair it forms with the row below.  A cell below a missing cell (row > 0)
+    then evaluates Eq. (2) with d1 = 0, tan(beta) = -tan(alpha) < 0, which no
+    window (its lower end clamped at 0) contains: the cell is kept."""
+    r = np.asarray(range_img)
+    meas = (r > 0) & np.isfinite(r)
+    keep = np.zeros_like(meas)
+    keep[..., 1:, :] = ~meas[..., :-1, :]          # the cell above is missing
+    return np.asarray(ground, dtype=bool) & ~keep
+
+
+def _sweep(n_scans: int, thresholds: List[float], depths: List[int], modes=(0,),
+           literal_g5: bool = False) -> List[dict]:
     import torch
     from paper_2003_00575_amd import flic, synth
     scans = [synth.large_batch_scan(100 + i, 0.5) for i in range(n_scans)]
     g = synth.ground_tables(scans[0].phi)
     dev = torch.device("cuda:0")
     rng = torch.from_numpy(np.stack([s.range_img for s in scans])).to(dev)
-    ours, _ = flic.ground_remove(rng, flic.ground_tables_to_device(g, dev), with_mask=False)
+    ours, mask = flic.ground_remove(rng, flic.ground_tables_to_device(g, dev))
     gt_removed = rng.clone()
     gt_removed[torch.from_numpy(np.stack([s.object_id == 0 for s in scans])).to(dev)] = 0.0
+    grounds = [("ground truth", gt_removed), ("Section III.A", ours)]
+    host_rng = rng.cpu().numpy()
+    measured_frac = float(((host_rng > 0) & np.isfinite(host_rng)).mean())
+    ext = mask.cpu().numpy().astype(bool)
+    print(f"Section III.A removes {ext.mean() / measured_frac:.4f} of the measurements", flush=True)
+    if literal_g5:
+        lit = literal_first_channel(host_rng, ext)
+        print(f"... with the literal first-channel rule: {lit.mean() / measured_frac:.4f}", flush=True)
+        lit_img = rng.clone()
+        lit_img[torch.from_numpy(lit).to(dev)] = 0.0
+        grounds.append(("III.A literal g5", lit_img))
     ctx = flic.Context(0)
     rows = []
-    for ground, imgs in (("ground truth", gt_removed), ("Section III.A", ours)):
+    for ground, imgs in grounds:
         for N, mc in [(N, mc) for N in depths for mc in modes if not (mc and N == 1)]:
             tabs = [synth.make_tables(s.phi, s.W, N) for s in scans]
             cv = [torch.from_numpy(t[0]).to(dev) for t in tabs]
@@ -123,9 +148,12 @@ def main(argv=None) -> int:
     ap.add_argument("--depths", default="1,2,3,5")
     ap.add_argument("--modes", default="0,1", help="skip-edge modes: 0 dense, 1 Map Connections")
     ap.add_argument("--json", default="")
+    ap.add_argument("--literal-g5", action="store_true",
+                    help="also score the literal first-channel rule of Section III.A")
     args = ap.parse_args(argv)
     rows = _sweep(args.scans, [float(x) for x in args.thresholds.split(",")],
-                  [int(x) for x in args.depths.split(",")], [int(x) for x in args.modes.split(",")])
+                  [int(x) for x in args.depths.split(",")], [int(x) for x in args.modes.split(",")],
+                  args.literal_g5)
     if args.json:
         with open(args.json, "w") as f:
             json.dump(rows, f)

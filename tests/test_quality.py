@@ -103,3 +103,20 @@ def test_brute_force(seed):
     assert set(got) == set(want)
     for g in want:
         assert got[g] == pytest.approx(want[g]), g
+
+
+def test_literal_first_channel_rule_keeps_cells_below_missing_ones():
+    """Under the literal reading only row 0 borrows the pair below; a cell of a
+    lower row whose upper neighbour is missing computes Eq. (2) with d1 = 0,
+    tan(beta) = -tan(alpha) < 0, and stays (hand-derived 3 x 3 case)."""
+    from paper_2003_00575_amd.quality import literal_first_channel
+    r = np.array([[0.0, 2.0, 2.0],
+                  [3.0, 0.0, 3.0],
+                  [4.0, 4.0, np.nan]], np.float32)
+    ext = np.array([[0, 1, 1],
+                    [1, 0, 1],
+                    [1, 1, 0]], bool)
+    want = np.array([[0, 1, 1],      # row 0: the first-channel rule, as extended
+                     [0, 0, 1],      # (1,0) lies under a missing cell: kept
+                     [1, 0, 0]], bool)   # (2,1) lies under a missing cell: kept
+    assert np.array_equal(literal_first_channel(r, ext), want)
