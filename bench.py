@@ -339,10 +339,16 @@ def main() -> int:
     ap.add_argument("--serve-speedups", default="16,32,48",
                     help="time-compression factors of the serving sweep")
     ap.add_argument("--no-stress", action="store_true", help="skip the union-find stress set")
+    ap.add_argument("--plan-parts", type=int, default=1,
+                    help="parallel graph branches per launch group in the large-batch plans")
+    ap.add_argument("--uneven-parts", type=int, default=3,
+                    help="parallel graph branches per launch group in the 256-scan uneven-batch plan")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="host threads of the oracle's all-core leg (0: every core this process may use, at most 16)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed batch and the per-kernel timing (for profilers)")
+    ap.add_argument("--profile-stress", action="store_true",
+                    help="only the union-find stress set's batched launches (for profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 128 MiB device copy (reference for byte counters)")
     ap.add_argument("--min-points", type=int, default=0,
@@ -371,6 +377,15 @@ def main() -> int:
     dev = torch.device("cuda:0")
     flic.lib()
 
+    if args.profile_stress:
+        from paper_2003_00575_amd import autotune
+        ctx = flic.Context(0)
+        autotune.apply_default(ctx)
+        st = stress_set(ctx, flic, synth, torch, dev, torch.cuda.current_stream(), reps=3)
+        print(json.dumps({"profile_stress": True, "labels_mismatching": st["labels_mismatching"],
+                          "runs": st["runs"]}), flush=True)
+        return 0 if st["labels_mismatching"] == 0 else 3
+
     # ---- inputs ------------------------------------------------------------
     t0 = time.time()
     host = [synth.large_batch_scan(i, 0.5) for i in range(N_SCANS)]
@@ -392,6 +407,7 @@ def main() -> int:
     autotune.apply_default(ctx)
     if args.tile_w:
         ctx.set_tile_width(args.tile_w)
+    ctx.set_plan_parts(args.plan_parts)
     plans = {(s, ti): ctx.plan(scans_for(s, ti)) for s in range(S) for ti in range(len(THRESHOLDS))}
     arrays = {(s, ti): flic.Context.scan_array(scans_for(s, ti)) for s in range(S) for ti in range(len(THRESHOLDS))}
     stream = torch.cuda.current_stream()
@@ -521,7 +537,10 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    ctx.set_plan_parts(args.uneven_parts)
     uneven = None if args.no_uneven else uneven_batch(ctx, flic, synth, torch, dev, stream)
+    if uneven:
+        uneven["plan_parts"] = args.uneven_parts
     ground = ground_extraction(flic, synth, torch, host, ranges, dev, stream)
     print(f"[bench] ground extraction: {ground['ms_per_call']} ms per 64-scan call, "
           f"{ground['roofline']['achieved']} GB/s", file=sys.stderr, flush=True)

@@ -111,6 +111,20 @@ hipError_t launch_cluster(const flic::BatchRef& ref, int tile_w, int skip, bool 
     }
 }
 
+hipError_t cluster_passes(int tile_w, int skip, bool sized, bool maps, int n_tiles, int n_scans,
+                          flic::PassLaunch* out) {
+    if (n_tiles <= 0 || n_scans <= 0) return hipErrorInvalidValue;
+    switch (tile_w * 2 + (maps ? 1 : 0)) {
+        case 128: return flic::cluster_passes_tw<64, false>(skip, sized, n_tiles, n_scans, out);
+        case 129: return flic::cluster_passes_tw<64, true>(skip, sized, n_tiles, n_scans, out);
+        case 256: return flic::cluster_passes_tw<128, false>(skip, sized, n_tiles, n_scans, out);
+        case 257: return flic::cluster_passes_tw<128, true>(skip, sized, n_tiles, n_scans, out);
+        case 512: return flic::cluster_passes_tw<256, false>(skip, sized, n_tiles, n_scans, out);
+        case 513: return flic::cluster_passes_tw<256, true>(skip, sized, n_tiles, n_scans, out);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t set_device(int dev) {
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
@@ -132,6 +146,7 @@ struct flic_ctx {
     size_t budget = 0;          // 0 = unlimited
     size_t used = 0;            // device bytes held by this context and its plans
     int tile_override = 0;
+    int plan_parts = 1;         // launch sequences per shape group in a plan
     struct TileRule { int32_t H, W, N, tile_w; };
     std::vector<TileRule> rules;   // exact-shape tile widths (autotuner output)
     static constexpr int kRing = 4;
@@ -247,7 +262,10 @@ struct Layout {
     std::vector<G> groups;
 };
 
-void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, char* scratch, Layout& L) {
+// parts > 1 splits every group into up to `parts` launch sequences over
+// consecutive member ranges (plans make them parallel graph branches).
+void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, char* scratch, Layout& L,
+                  int parts = 1) {
     L.blob.clear();
     L.groups.clear();
     std::vector<char*> base(n);
@@ -262,35 +280,41 @@ void build_layout(const flic_ctx* ctx, const flic_scan* scans, int32_t n, char* 
     constexpr int kShapes = 3 * FLIC_MAX_SKIP;
     for (int gi = 0; gi < 4 * kShapes; ++gi) {
         const int gw = gi % kShapes, mode = gi / kShapes;
-        Layout::G g{widths[gw / FLIC_MAX_SKIP], 1 + gw % FLIC_MAX_SKIP, (mode & 1) != 0, (mode & 2) != 0,
-                    0, 0, 0, {}};
+        Layout::G all{widths[gw / FLIC_MAX_SKIP], 1 + gw % FLIC_MAX_SKIP, (mode & 1) != 0, (mode & 2) != 0,
+                      0, 0, 0, {}};
         for (int32_t i = 0; i < n; ++i)
-            if (choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth) == g.tile_w &&
-                scans[i].skip_depth == g.skip && sized(scans[i]) == g.sized && maps(scans[i]) == g.maps)
-                g.members.push_back(i);
-        if (g.members.empty()) continue;
-        std::vector<ScanDesc> descs;
-        std::vector<int32_t> map;
-        int32_t tiles = 0;
-        for (size_t m = 0; m < g.members.size(); ++m) {
-            const int i = g.members[m];
-            ScanDesc d = make_desc(scans[i], g.tile_w, tiles, base[i]);
-            const int32_t t = d.tiles_x * d.tiles_y;
-            for (int32_t k = 0; k < t; ++k) map.push_back((int32_t)m);
-            tiles += t;
-            descs.push_back(d);
+            if (choose_tile_w(ctx, scans[i].H, scans[i].W, scans[i].skip_depth) == all.tile_w &&
+                scans[i].skip_depth == all.skip && sized(scans[i]) == all.sized && maps(scans[i]) == all.maps)
+                all.members.push_back(i);
+        if (all.members.empty()) continue;
+        const size_t np = std::min<size_t>(std::max(parts, 1), all.members.size());
+        for (size_t part = 0; part < np; ++part) {
+            Layout::G g = all;
+            g.members.assign(all.members.begin() + all.members.size() * part / np,
+                             all.members.begin() + all.members.size() * (part + 1) / np);
+            std::vector<ScanDesc> descs;
+            std::vector<int32_t> map;
+            int32_t tiles = 0;
+            for (size_t m = 0; m < g.members.size(); ++m) {
+                const int i = g.members[m];
+                ScanDesc d = make_desc(scans[i], g.tile_w, tiles, base[i]);
+                const int32_t t = d.tiles_x * d.tiles_y;
+                for (int32_t k = 0; k < t; ++k) map.push_back((int32_t)m);
+                tiles += t;
+                descs.push_back(d);
+            }
+            g.n_tiles = tiles;
+            auto align = [&](size_t a) { L.blob.resize((L.blob.size() + a - 1) / a * a); };
+            align(256);
+            g.desc_off = L.blob.size();
+            L.blob.resize(L.blob.size() + descs.size() * sizeof(ScanDesc));
+            memcpy(L.blob.data() + g.desc_off, descs.data(), descs.size() * sizeof(ScanDesc));
+            align(256);
+            g.map_off = L.blob.size();
+            L.blob.resize(L.blob.size() + map.size() * sizeof(int32_t));
+            memcpy(L.blob.data() + g.map_off, map.data(), map.size() * sizeof(int32_t));
+            L.groups.push_back(std::move(g));
         }
-        g.n_tiles = tiles;
-        auto align = [&](size_t a) { L.blob.resize((L.blob.size() + a - 1) / a * a); };
-        align(256);
-        g.desc_off = L.blob.size();
-        L.blob.resize(L.blob.size() + descs.size() * sizeof(ScanDesc));
-        memcpy(L.blob.data() + g.desc_off, descs.data(), descs.size() * sizeof(ScanDesc));
-        align(256);
-        g.map_off = L.blob.size();
-        L.blob.resize(L.blob.size() + map.size() * sizeof(int32_t));
-        memcpy(L.blob.data() + g.map_off, map.data(), map.size() * sizeof(int32_t));
-        L.groups.push_back(std::move(g));
     }
 }
 
@@ -323,6 +347,39 @@ flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t st
                                stream, ev));
     }
     return FLIC_OK;
+}
+
+// The plan's graph: per group (a shape group, or a part of one) a chain of
+// its three pass nodes; the chains share no edge, so one group's
+// latency-bound scan merge overlaps the other groups' tile and relabel
+// passes.  Built node by node (no stream capture, no extra streams).
+hipError_t build_plan_graph(const Layout& L, const char* dev_base, hipGraph_t* graph) {
+    hipError_t e = hipGraphCreate(graph, 0);
+    if (e != hipSuccess) return e;
+    for (const auto& g : L.groups) {
+        flic::BatchRef ref{};
+        ref.descs = reinterpret_cast<const ScanDesc*>(dev_base + g.desc_off);
+        ref.block_scan = reinterpret_cast<const int32_t*>(dev_base + g.map_off);
+        flic::PassLaunch pass[flic::kPasses];
+        e = cluster_passes(g.tile_w, g.skip, g.sized, g.maps, g.n_tiles, (int)g.members.size(), pass);
+        if (e != hipSuccess) return e;
+        hipGraphNode_t prev = nullptr;
+        for (int k = 0; k < flic::kPasses; ++k) {
+            void* args[] = {&ref};                   // copied into the node
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void*>(pass[k].fn);
+            kp.gridDim = dim3(pass[k].grid);
+            kp.blockDim = dim3(pass[k].block);
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            e = hipGraphAddKernelNode(&node, *graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+            if (e != hipSuccess) return e;
+            prev = node;
+        }
+    }
+    return hipSuccess;
 }
 
 size_t round_cap(size_t need) {
@@ -435,6 +492,13 @@ flic_status flic_ctx_set_tile_rule(flic_ctx* ctx, int32_t H, int32_t W, int32_t 
     for (size_t i = 0; i < v.size(); ++i)
         if (v[i].H == H && v[i].W == W && v[i].N == skip_depth) { v.erase(v.begin() + i); break; }
     if (tile_w) v.push_back({H, W, skip_depth, tile_w});
+    return FLIC_OK;
+}
+
+flic_status flic_ctx_set_plan_parts(flic_ctx* ctx, int32_t parts) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    if (parts < 1 || parts > 64) return fail(FLIC_EINVAL, "parts %d outside 1..64", parts);
+    ctx->plan_parts = parts;
     return FLIC_OK;
 }
 
@@ -598,7 +662,8 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, f
     flic_status st = check_scans(scans, n);
     if (st != FLIC_OK) return st;
     Layout L;
-    build_layout(ctx, scans, n, nullptr, L);
+    const int parts = ctx->plan_parts;
+    build_layout(ctx, scans, n, nullptr, L, parts);
     const size_t scratch = scratch_bytes(ctx, scans, n);
     if (ctx->budget && ctx->used + L.blob.size() + scratch > ctx->budget)
         return fail(FLIC_ENOMEM, "plan of %zu bytes exceeds the HBM budget", L.blob.size() + scratch);
@@ -623,7 +688,7 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, f
     }
     p->scratch_bytes = scratch;
     ctx->used += scratch;
-    build_layout(ctx, scans, n, static_cast<char*>(p->scratch), L);
+    build_layout(ctx, scans, n, static_cast<char*>(p->scratch), L, parts);
     p->blob_bytes = L.blob.size();
     for (const auto& g : L.groups)
         p->groups.push_back({g.tile_w, g.skip, g.sized, g.maps, g.n_tiles, g.desc_off, g.members});
@@ -639,18 +704,8 @@ flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, f
     memcpy(p->host_blob, L.blob.data(), p->blob_bytes);
     if (hipMemcpy(p->dev_mem, p->host_blob, p->blob_bytes, hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(FLIC_EHIP, "descriptor upload failed"));
-    hipStream_t cs;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
-        return cleanup(fail(FLIC_EHIP, "hipStreamCreate failed"));
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        flic_status s2 = enqueue_layout(L, static_cast<const char*>(p->dev_mem), cs, nullptr);
-        hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
-        if (s2 != FLIC_OK) { (void)hipStreamDestroy(cs); return cleanup(s2); }
-        e = e2;
-    }
-    (void)hipStreamDestroy(cs);
-    if (e != hipSuccess) return cleanup(fail(FLIC_EHIP, "graph capture failed: %s", hipGetErrorString(e)));
+    hipError_t e = build_plan_graph(L, static_cast<const char*>(p->dev_mem), &p->graph);
+    if (e != hipSuccess) return cleanup(fail(FLIC_EHIP, "plan graph: %s", hipGetErrorString(e)));
     e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return cleanup(fail(FLIC_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e)));
     if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)

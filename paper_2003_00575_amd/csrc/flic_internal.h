@@ -114,6 +114,15 @@ template <int TW, bool MAPS>
 hipError_t launch_cluster_tw(const BatchRef& ref, int skip, bool sized, int n_tiles, int n_scans,
                              hipStream_t stream, hipEvent_t* events);
 
+// The same three passes as kernel entry points and launch shapes (each takes
+// one BatchRef argument, no dynamic LDS), for building graph nodes.
+struct PassLaunch {
+    const void* fn;
+    unsigned grid, block;
+};
+template <int TW, bool MAPS>
+hipError_t cluster_passes_tw(int skip, bool sized, int n_tiles, int n_scans, PassLaunch* out);
+
 
 
 // Ground extraction over n scans of one shape sharing one sensor's tables:

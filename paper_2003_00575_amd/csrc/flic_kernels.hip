@@ -73,7 +73,7 @@ __device__ __forceinline__ bool connected(float d1, float d2, float two_cos, flo
 
 // A measurement is a positive normal or subnormal number (one class test).
 __device__ __forceinline__ float measurement_or_nan(float r) {
-    return __builtin_amdgcn_class(r, (1 << 7) | (1 << 8)) ? r : __builtin_nanf("");
+    return __builtin_amdgcn_classf(r, (1 << 7) | (1 << 8)) ? r : __builtin_nanf("");
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
@@ -101,6 +101,13 @@ __device__ __forceinline__ uint64_t row_mask(unsigned v, int q) {
     const uint32_t lo = __builtin_amdgcn_readlane((int)v, q);
     const uint32_t hi = __builtin_amdgcn_readlane((int)v, q + 1);
     return ((uint64_t)hi << 32) | lo;
+}
+
+// Write the wave-uniform value v into lane l (uniform) of w: one v_writelane
+// (the lane select goes through M0: one scalar operand per VALU instruction).
+__device__ __forceinline__ unsigned write_lane(unsigned w, unsigned v, int l) {
+    asm volatile("v_writelane_b32 %0, %1, m0" : "+v"(w) : "s"(v), "{m0}"(l));
+    return w;
 }
 
 __device__ __forceinline__ uint64_t lanes_le(int lane) {
@@ -428,18 +435,18 @@ void k_tile_label(BatchRef ref) {
         // a run whose head has a (pruned) direct vertical edge takes the strip
         // root above the head; any other run is a new strip root
         const bool up = lane_bit(link);
-        const int got = __shfl(up ? above : kNoRoot, head);
+        const int got = __builtin_amdgcn_ds_bpermute(head << 2, up ? above : kNoRoot);
         const int root = got != kNoRoot ? got : r * TW + ch * 64 + head;
         par[r * TW + c] = root;                           // (never read for a missing pixel)
         if (up && above != root) t |= 2u;                // may join another tree above
         const uint64_t starts = vmask & ~(h1 << 1);       // heads of the row's runs
         const uint64_t sroots = starts & ~ballot(got != kNoRoot);
-        words = lane_bit(1ull << (4 * j + 0)) ? (unsigned)starts : words;
-        words = lane_bit(1ull << (4 * j + 1)) ? (unsigned)(starts >> 32) : words;
-        words = lane_bit(1ull << (4 * j + 2)) ? (unsigned)vmask : words;
-        words = lane_bit(1ull << (4 * j + 3)) ? (unsigned)(vmask >> 32) : words;
-        sroot_words = lane_bit(1ull << (2 * j + 0)) ? (unsigned)sroots : sroot_words;
-        sroot_words = lane_bit(1ull << (2 * j + 1)) ? (unsigned)(sroots >> 32) : sroot_words;
+        words = write_lane(words, (unsigned)starts, 4 * j + 0);
+        words = write_lane(words, (unsigned)(starts >> 32), 4 * j + 1);
+        words = write_lane(words, (unsigned)vmask, 4 * j + 2);
+        words = write_lane(words, (unsigned)(vmask >> 32), 4 * j + 3);
+        sroot_words = write_lane(sroot_words, (unsigned)sroots, 2 * j + 0);
+        sroot_words = write_lane(sroot_words, (unsigned)(sroots >> 32), 2 * j + 1);
         above = root;                                     // read only below a measurement
         // materialise this row's per-lane results here: otherwise the compiler
         // sinks them to their uses after the barrier and keeps the 64-bit
@@ -552,7 +559,8 @@ void k_tile_label(BatchRef ref) {
         const bool head = lane_bit(starts);
         if (head && j < rows) {
             const unsigned root = node[j];
-            const int k = __popcll(starts & below);      // run index in the chunk
+            const int k = __builtin_amdgcn_mbcnt_hi((unsigned)(starts >> 32),
+                              __builtin_amdgcn_mbcnt_lo((unsigned)starts, 0u));   // run index in the chunk
             if (k < kRunHead)
                 (runs + (mrow + j) * kRunHead)[k] = (uint16_t)root;
             else
@@ -1165,6 +1173,30 @@ hipError_t launch_twn(const BatchRef& ref, int n_tiles, int n_scans, hipStream_t
     return hipGetLastError();
 }
 
+template <int TW, int N, bool SIZE, bool MAPS>
+void passes_twn(int n_tiles, int n_scans, PassLaunch* out) {
+    out[0] = {reinterpret_cast<const void*>(&k_tile_label<TW, N, SIZE, MAPS>), (unsigned)n_tiles,
+              (unsigned)kLabelThreads};
+    out[1] = {reinterpret_cast<const void*>(&k_scan_merge<TW, N, SIZE, MAPS>), (unsigned)n_scans,
+              (unsigned)kMergeThreads};
+    out[2] = {reinterpret_cast<const void*>(&k_relabel<TW, SIZE>), (unsigned)n_tiles, (unsigned)kRelabelThreads};
+}
+
+template <int TW, bool SIZE, bool MAPS>
+hipError_t passes_tws(int skip, int n_tiles, int n_scans, PassLaunch* out) {
+    switch (skip) {
+        case 1: passes_twn<TW, 1, SIZE, false>(n_tiles, n_scans, out); return hipSuccess;
+        case 2: passes_twn<TW, 2, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
+        case 3: passes_twn<TW, 3, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
+        case 4: passes_twn<TW, 4, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
+        case 5: passes_twn<TW, 5, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
+        case 6: passes_twn<TW, 6, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
+        case 7: passes_twn<TW, 7, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
+        case 8: passes_twn<TW, 8, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int TW, bool SIZE, bool MAPS>
 hipError_t launch_tws(const BatchRef& ref, int skip, int n_tiles, int n_scans, hipStream_t stream,
                       hipEvent_t* ev) {
@@ -1192,8 +1224,15 @@ hipError_t launch_cluster_tw(const BatchRef& ref, int skip, bool sized, int n_ti
                  : launch_tws<TW, false, MAPS>(ref, skip, n_tiles, n_scans, stream, events);
 }
 
+template <int TW, bool MAPS>
+hipError_t cluster_passes_tw(int skip, bool sized, int n_tiles, int n_scans, PassLaunch* out) {
+    return sized ? passes_tws<TW, true, MAPS>(skip, n_tiles, n_scans, out)
+                 : passes_tws<TW, false, MAPS>(skip, n_tiles, n_scans, out);
+}
+
 #define FLIC_INSTANTIATE(TW, MAPS) \
-    template hipError_t launch_cluster_tw<TW, MAPS>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*);
+    template hipError_t launch_cluster_tw<TW, MAPS>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*); \
+    template hipError_t cluster_passes_tw<TW, MAPS>(int, bool, int, int, PassLaunch*);
 #if !defined(FLIC_MAPS) || FLIC_MAPS == 0
 #if !defined(FLIC_TILE_W) || FLIC_TILE_W == 64
 FLIC_INSTANTIATE(64, false)

@@ -84,6 +84,8 @@ def lib() -> ctypes.CDLL:
     L.flic_set_tile_override.restype = i32
     L.flic_ctx_set_tile_rule.argtypes = [vp, i32, i32, i32, i32]
     L.flic_ctx_set_tile_rule.restype = i32
+    L.flic_ctx_set_plan_parts.argtypes = [vp, i32]
+    L.flic_ctx_set_plan_parts.restype = i32
     L.flic_ctx_tile_for.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i32)]
     L.flic_ctx_tile_for.restype = i32
     L.flic_batch_bytes.argtypes = [vp, ctypes.POINTER(_Scan), i32, ctypes.POINTER(ctypes.c_size_t),
@@ -234,6 +236,11 @@ class Context:
     def set_tile_rule(self, H: int, W: int, skip_depth: int, tile_w: int) -> None:
         """Use tile_w columns per tile for scans of exactly this shape (0 removes)."""
         _check(lib().flic_ctx_set_tile_rule(self.handle, int(H), int(W), int(skip_depth), int(tile_w)))
+
+    def set_plan_parts(self, parts: int) -> None:
+        """Plans created afterwards split each launch group into up to
+        `parts` parallel graph branches (1 = one sequence per group)."""
+        _check(lib().flic_ctx_set_plan_parts(self.handle, int(parts)))
 
     def tile_for(self, H: int, W: int, skip_depth: int) -> int:
         out = ctypes.c_int32()

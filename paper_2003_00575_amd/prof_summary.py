@@ -11,9 +11,10 @@ dispatch of every collected counter (from *_counter_collection.csv).
 
 writes one record for a workload: mean kernel durations, HBM bytes per
 dispatch from FETCH_SIZE and WRITE_SIZE (each scaled by what the counter reads
-for the 128 MiB device copy the profiled program runs once), optional SQ
-instruction counters, the commands that produced the inputs, the SHA-256 of
-the kernel source, and a final "json:" line that bench.py reads.
+for the 128 MiB device copy the profiled program runs once), optional counter
+passes (--sq, repeatable: SQ instructions, TCC hits and atomics, occupancy),
+the commands that produced the inputs, the SHA-256 of the kernel source, and a
+final "json:" line that bench.py reads.
 """
 from __future__ import annotations
 
@@ -112,7 +113,12 @@ def record(args) -> str:
     kt = durations(args.kernel_trace)
     fe = counters(args.fetch)
     wr = counters(args.write)
-    sq = counters(args.sq) if args.sq else {}
+    # instruction / cache / occupancy counters: one or more passes, merged
+    sq_dirs = [args.sq] if isinstance(args.sq, str) else list(args.sq or [])
+    sq = {}
+    for d in sq_dirs:
+        for key, vals in counters(d).items():
+            sq.setdefault(key, {}).update(vals)
     (_, fetch_copy_kib) = _calibration_copy(fe, "FETCH_SIZE")
     (_, write_copy_kib) = _calibration_copy(wr, "WRITE_SIZE")
     f_fetch = COPY_BYTES / (fetch_copy_kib * 1024.0)
@@ -154,7 +160,7 @@ def record(args) -> str:
         lines.append(f"{short:13s} {e['kernel']:24s} {e['grid']:9d} {e['dispatches']:4d} {e['mean_us']:8.2f} "
                      f"{e['min_us']:8.2f} {fm:>9s} {wm:>9s}")
     if sq:
-        lines += ["", "SQ counters per dispatch:"]
+        lines += ["", "counters per dispatch (SQ instructions and waits, TCC hits / misses / atomics, occupancy):"]
         for short, e in kernels.items():
             if "sq" in e:
                 lines.append(f"{short:13s} " + "  ".join(f"{c}={x:.4g}" for c, x in e["sq"].items()))
@@ -188,7 +194,8 @@ def main(argv=None) -> int:
     ap.add_argument("--kernel-trace", required=True)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
-    ap.add_argument("--sq")
+    ap.add_argument("--sq", action="append", default=[],
+                    help="a directory of counter passes (repeatable; all are merged per kernel)")
     ap.add_argument("--command", action="append", default=[])
     args = ap.parse_args(argv)
     text = record(args)

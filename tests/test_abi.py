@@ -115,3 +115,7 @@ def test_noalloc_rejects_before_any_hip_call(L):
     assert flic.cluster_noalloc_raw(R, 4, 64, CV, CH, 0.5, 9, LBL, 0) == flic.FLIC_EINVAL
     assert flic.cluster_noalloc_raw(R, 1024, 4096, CV, CH, 0.5, 3, LBL, 0) == flic.FLIC_EINVAL
     assert "scratch" in flic.last_error()
+
+
+def test_plan_parts_validated(L):
+    assert L.flic_ctx_set_plan_parts(None, 3) == flic.FLIC_EINVAL

@@ -250,3 +250,23 @@ def test_plan_relaunch_on_two_streams(flic):
         for i, d in enumerate(devs):
             assert_same(d.labels.cpu().numpy(), want[i], f"rep {rep} scan {i}")
     plan.close()
+
+
+@pytest.mark.parametrize("parts", [2, 3, 7])
+def test_plan_parts_as_parallel_branches(flic, parts):
+    """A plan whose launch groups are split into parallel graph branches
+    gives the same labels as the oracle (mixed shapes, relaunched)."""
+    scans = [synth.mixed_scan(i) for i in range(0, 40)]
+    want = [oracle.cluster_scan(s) for s in scans]
+    ctx = flic.Context(0)
+    ctx.set_plan_parts(parts)
+    devs = [flic.to_device(s) for s in scans]
+    plan = ctx.plan(devs)
+    for rep in range(2):
+        for d in devs:
+            d.labels.fill_(-9)
+        plan.relaunch()
+        torch.cuda.synchronize()
+        for i, d in enumerate(devs):
+            assert_same(d.labels.cpu().numpy(), want[i], f"parts {parts} rep {rep} scan {i}")
+    plan.close()
