@@ -103,11 +103,17 @@ __device__ __forceinline__ uint64_t row_mask(unsigned v, int q) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Write the wave-uniform value v into lane l (uniform) of w: one v_writelane
-// (the lane select goes through M0: one scalar operand per VALU instruction).
+// Write the wave-uniform value v into lane l of w: one v_writelane.  l must
+// fold to a constant (unrolled loops): as an inline constant the lane select
+// needs no second scalar operand (one scalar read per VALU instruction).
 __device__ __forceinline__ unsigned write_lane(unsigned w, unsigned v, int l) {
-    asm volatile("v_writelane_b32 %0, %1, m0" : "+v"(w) : "s"(v), "{m0}"(l));
+    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(w) : "s"(v), "i"(l));
     return w;
+}
+
+// Set bits of m in the lanes below this one, plus acc (two VALU ops).
+__device__ __forceinline__ int count_below(uint64_t m, unsigned acc = 0u) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, acc));
 }
 
 __device__ __forceinline__ uint64_t lanes_le(int lane) {
@@ -241,6 +247,7 @@ void k_tile_label(BatchRef ref) {
     static_assert(kTilePx <= kNoRoot, "tile indices fit 16 bits");
     __shared__ float rs[LR * RS];
     __shared__ int par[kTilePx];
+    __shared__ int run_root[kLabelWaves * 65];   // per wavefront: strip root of run k (1..64) of the row
 
     ScanDesc d;
     int tile;
@@ -320,7 +327,6 @@ void k_tile_label(BatchRef ref) {
         slot_v[u] = (it < n_slots && border_slot<TW, N>(it, tw, th, rr, cc)) ? rs[(rr + N) * RS + cc] : nan;
     }
 
-    const uint64_t le = lanes_le(lane);
     const float* at = rs + N * RS + c;                    // at[x * RS + k]: tile row x, column c + k
     // MAPS: bit k set when this lane's column is a multiple of k
     [[maybe_unused]] unsigned col_on_map = 0;
@@ -431,15 +437,20 @@ void k_tile_label(BatchRef ref) {
                 if (lane_bit(vneed)) t |= 1u << k;
             }
         }
-        const int head = 63 - __clzll(~(h1 << 1) & le);   // first pixel of the run
-        // a run whose head has a (pruned) direct vertical edge takes the strip
-        // root above the head; any other run is a new strip root
-        const bool up = lane_bit(link);
-        const int got = __builtin_amdgcn_ds_bpermute(head << 2, up ? above : kNoRoot);
-        const int root = got != kNoRoot ? got : r * TW + ch * 64 + head;
-        par[r * TW + c] = root;                           // (never read for a missing pixel)
-        if (up && above != root) t |= 2u;                // may join another tree above
+        // Runs: a run head with a (pruned) direct vertical edge takes the
+        // strip root above it, any other head is a new strip root.  Each head
+        // puts its root in its run's slot (run number = heads at or below the
+        // lane, 1-based), and every lane of the run reads it back.
         const uint64_t starts = vmask & ~(h1 << 1);       // heads of the row's runs
+        const bool up = lane_bit(link);
+        const int got = up ? above : kNoRoot;             // read at heads only
+        const int run = count_below(starts >> 1, (unsigned)(starts & 1u));
+        int* slot = run_root + wave * 65 + run;
+        if (lane_bit(starts)) *slot = got != kNoRoot ? got : r * TW + c;
+        asm volatile("" ::: "memory");                    // one store, then one load for all lanes
+        const int root = *slot;                           // (garbage for a missing pixel: never read)
+        par[r * TW + c] = root;
+        if (up && above != root) t |= 2u;                // may join another tree above
         const uint64_t sroots = starts & ~ballot(got != kNoRoot);
         words = write_lane(words, (unsigned)starts, 4 * j + 0);
         words = write_lane(words, (unsigned)(starts >> 32), 4 * j + 1);
@@ -477,7 +488,6 @@ void k_tile_label(BatchRef ref) {
     static_assert(kTilePx <= (1 << 13) && 2 * kMaxSkip <= 32 - 13, "queue entry packing");
     static_assert(kLabelWaves * kRowsPerWave * 64 <= LR * RS, "queues fit the range buffer");
     int* queue = reinterpret_cast<int*>(rs) + wave * (kRowsPerWave * 64);
-    const uint64_t below = le >> 1;                       // lanes < lane
 
     // Join: the strip's pixels with join bits (index | bits << 13), one lane
     // per pixel (about three per strip).
@@ -486,7 +496,7 @@ void k_tile_label(BatchRef ref) {
 #pragma unroll
         for (int j = 0; j < kRowsPerWave; ++j) {
             const uint64_t m = ballot(todo[j] != 0);
-            if (todo[j]) queue[count + __popcll(m & below)] = ((R0 + j) * TW + c) | (int)(todo[j] << 13);
+            if (todo[j]) queue[count + count_below(m)] = ((R0 + j) * TW + c) | (int)(todo[j] << 13);
             count += __popcll(m);
         }
         __builtin_amdgcn_wave_barrier();
@@ -511,9 +521,8 @@ void k_tile_label(BatchRef ref) {
         int count = 0;
 #pragma unroll
         for (int j = 0; j < kRowsPerWave; ++j) {
-            const bool sr = lane_bit(row_mask(sroot_words, 2 * j));
-            const uint64_t m = ballot(sr);
-            if (sr) queue[count + __popcll(m & below)] = (R0 + j) * TW + c;
+            const uint64_t m = row_mask(sroot_words, 2 * j);
+            if (lane_bit(m)) queue[count + count_below(m)] = (R0 + j) * TW + c;
             count += __popcll(m);
         }
         __builtin_amdgcn_wave_barrier();
@@ -543,28 +552,30 @@ void k_tile_label(BatchRef ref) {
     const gptr<int> labels = global(d.labels);
     const unsigned mrow = (c0 / 64 + ch) * H + r0 + R0;   // chunk-major row index of the strip
     const unsigned lbase = base + R0 * W + ch * 64;
-    // final roots of the strip's run heads: two reads (head -> strip root ->
-    // final root), the 8 rows' reads issued together
+    const gptr<uint16_t> strip_runs = runs + mrow * kRunHead;
+    // final roots of the strip's pixels: two reads (pixel -> strip root ->
+    // final root; a missing pixel's entry is garbage, hence the index mask),
+    // the 8 rows' reads issued together; used at run heads
     int node[kRowsPerWave];
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j)
-        node[j] = lane_bit(row_mask(words, 4 * j)) ? lds_load(&par[(R0 + j) * TW + c]) : 0;
+    for (int j = 0; j < kRowsPerWave; ++j) node[j] = lds_load(&par[(R0 + j) * TW + c]);
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) node[j] = lds_load(&par[node[j]]);
+    for (int j = 0; j < kRowsPerWave; ++j) node[j] = lds_load(&par[node[j] & (kTilePx - 1)]);
     // run roots; the masks of all rows in one store (words, built above)
     [[maybe_unused]] unsigned own_root = 0;              // SIZE: rows where this lane is a tile root
+    [[maybe_unused]] const uint64_t le = lanes_le(lane);
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
         const uint64_t starts = row_mask(words, 4 * j);
         const bool head = lane_bit(starts);
-        if (head && j < rows) {
-            const unsigned root = node[j];
-            const int k = __builtin_amdgcn_mbcnt_hi((unsigned)(starts >> 32),
-                              __builtin_amdgcn_mbcnt_lo((unsigned)starts, 0u));   // run index in the chunk
-            if (k < kRunHead)
-                (runs + (mrow + j) * kRunHead)[k] = (uint16_t)root;
-            else
-                (labels + (lbase + j * W))[k] = root;
+        const unsigned root = node[j];
+        const int k = count_below(starts);               // run index in the chunk
+        // (a row outside the image has no run heads: its ranges are NaN)
+        if (head && k < kRunHead) strip_runs[j * kRunHead + k] = (uint16_t)root;
+        if (__popc((unsigned)starts) + __popc((unsigned)(starts >> 32)) > kRunHead) {   // rare: many runs
+            if (head && k >= kRunHead) (labels + (lbase + j * W))[k] = root;
+        }
+        if (head) {
             if constexpr (SIZE) {
                 // the run ends before the next run head or missing pixel of
                 // the chunk (runs never cross a chunk border)
