@@ -111,18 +111,21 @@ hipError_t launch_cluster(const flic::BatchRef& ref, int tile_w, int skip, bool 
     }
 }
 
-hipError_t cluster_passes(int tile_w, int skip, bool sized, bool maps, int n_tiles, int n_scans,
-                          flic::PassLaunch* out) {
-    if (n_tiles <= 0 || n_scans <= 0) return hipErrorInvalidValue;
+// The kernels of one launch group (count in *n_out), for graph nodes.
+hipError_t cluster_passes(int tile_w, int skip, bool sized, bool maps, int n_tiles, flic::PassLaunch* out,
+                          int* n_out) {
+    *n_out = 0;
+    if (n_tiles <= 0) return hipErrorInvalidValue;
     switch (tile_w * 2 + (maps ? 1 : 0)) {
-        case 128: return flic::cluster_passes_tw<64, false>(skip, sized, n_tiles, n_scans, out);
-        case 129: return flic::cluster_passes_tw<64, true>(skip, sized, n_tiles, n_scans, out);
-        case 256: return flic::cluster_passes_tw<128, false>(skip, sized, n_tiles, n_scans, out);
-        case 257: return flic::cluster_passes_tw<128, true>(skip, sized, n_tiles, n_scans, out);
-        case 512: return flic::cluster_passes_tw<256, false>(skip, sized, n_tiles, n_scans, out);
-        case 513: return flic::cluster_passes_tw<256, true>(skip, sized, n_tiles, n_scans, out);
-        default: return hipErrorInvalidValue;
+        case 128: *n_out = flic::cluster_passes_tw<64, false>(skip, sized, n_tiles, out); break;
+        case 129: *n_out = flic::cluster_passes_tw<64, true>(skip, sized, n_tiles, out); break;
+        case 256: *n_out = flic::cluster_passes_tw<128, false>(skip, sized, n_tiles, out); break;
+        case 257: *n_out = flic::cluster_passes_tw<128, true>(skip, sized, n_tiles, out); break;
+        case 512: *n_out = flic::cluster_passes_tw<256, false>(skip, sized, n_tiles, out); break;
+        case 513: *n_out = flic::cluster_passes_tw<256, true>(skip, sized, n_tiles, out); break;
+        default: break;
     }
+    return *n_out > 0 ? hipSuccess : hipErrorInvalidValue;
 }
 
 hipError_t set_device(int dev) {
@@ -350,9 +353,8 @@ flic_status enqueue_layout(const Layout& L, const char* dev_base, hipStream_t st
 }
 
 // The plan's graph: per group (a shape group, or a part of one) a chain of
-// its three pass nodes; the chains share no edge, so one group's
-// latency-bound scan merge overlaps the other groups' tile and relabel
-// passes.  Built node by node (no stream capture, no extra streams).
+// its pass kernels; the chains share no edge, so the groups' passes overlap
+// one another.  Built node by node (no stream capture, no extra streams).
 hipError_t build_plan_graph(const Layout& L, const char* dev_base, hipGraph_t* graph) {
     hipError_t e = hipGraphCreate(graph, 0);
     if (e != hipSuccess) return e;
@@ -360,11 +362,12 @@ hipError_t build_plan_graph(const Layout& L, const char* dev_base, hipGraph_t* g
         flic::BatchRef ref{};
         ref.descs = reinterpret_cast<const ScanDesc*>(dev_base + g.desc_off);
         ref.block_scan = reinterpret_cast<const int32_t*>(dev_base + g.map_off);
-        flic::PassLaunch pass[flic::kPasses];
-        e = cluster_passes(g.tile_w, g.skip, g.sized, g.maps, g.n_tiles, (int)g.members.size(), pass);
+        flic::PassLaunch pass[flic::kMaxPassKernels];
+        int n_pass = 0;
+        e = cluster_passes(g.tile_w, g.skip, g.sized, g.maps, g.n_tiles, pass, &n_pass);
         if (e != hipSuccess) return e;
         hipGraphNode_t prev = nullptr;
-        for (int k = 0; k < flic::kPasses; ++k) {
+        for (int k = 0; k < n_pass; ++k) {
             void* args[] = {&ref};                   // copied into the node
             hipKernelNodeParams kp{};
             kp.func = const_cast<void*>(pass[k].fn);

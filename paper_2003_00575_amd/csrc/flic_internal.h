@@ -26,9 +26,11 @@ constexpr int kRunHead = 16;
 //   runs    [chunks_per_row][H][kRunHead] uint16: tile-local root of the
 //           chunk's k-th run (k < kRunHead); runs k >= kRunHead keep theirs
 //           at position k of the chunk's label segment.
-//   parent  [H*W] int32, used only at tile-root positions, and only by
-//           pass 2 when the scan's border roots overflow its LDS tables:
-//           the union-find of the tile components in global memory.
+//   parent  [H*W] int32, used only at the positions of tile roots that
+//           touch a tile border: the union-find of the tile components.
+//           Pass 1 makes each such root its own parent, pass 2 joins them
+//           (a root always under a smaller one), pass 3 reads the roots.
+//           Other entries are never read.
 //   counts  [H*W] int32 (scans with a size threshold only), used only at
 //           tile-root positions: pass 1 stores each tile component's pixel
 //           count there, pass 2 adds every non-final root's count to its
@@ -38,8 +40,9 @@ constexpr int kRunHead = 16;
 //           first (side 0) and last (side 1) N columns of each tile.
 //   brow_v / brow_r  [tiles][2][N][tile_w]: the same for the first and last N
 //           rows; present only when the scan has more than one tile row.
-//           Pass 2 overwrites each used slot's range (bcol_v / brow_v) with
-//           the int32 final root of its provisional root, for pass 3.
+//           With a size threshold, pass 2 overwrites each used slot's range
+//           (bcol_v / brow_v) with the int32 final root of its provisional
+//           root, for pass 3.
 // Border slots outside the image part of a tile hold (NaN, -1).
 struct ScanDesc {
     const float* range;     // [H][W]
@@ -103,7 +106,7 @@ inline ScratchLayout scratch_layout(int H, int W, int N, int tile_w, bool sized)
 
 constexpr int kPasses = 3;
 
-// Enqueue the three passes (tile labelling, scan merge, relabel) for
+// Enqueue the three passes (tile labelling, border joins, relabel) for
 // `n_scans` scans with `n_tiles` tiles in total, of tile width TW (64, 128
 // or 256) and skip depth `skip` (1..kMaxSkip); `sized` selects the kernels
 // that also count component sizes and apply each scan's min_points; MAPS the
@@ -114,14 +117,17 @@ template <int TW, bool MAPS>
 hipError_t launch_cluster_tw(const BatchRef& ref, int skip, bool sized, int n_tiles, int n_scans,
                              hipStream_t stream, hipEvent_t* events);
 
-// The same three passes as kernel entry points and launch shapes (each takes
-// one BatchRef argument, no dynamic LDS), for building graph nodes.
+// The kernels of those passes, in launch order, as entry points and launch
+// shapes (each takes one BatchRef argument, no dynamic LDS), for building
+// graph nodes: the tile pass, the border joins, with a size threshold the
+// border finalize, the relabel.  Returns how many (0 for an invalid skip).
+constexpr int kMaxPassKernels = 4;
 struct PassLaunch {
     const void* fn;
     unsigned grid, block;
 };
 template <int TW, bool MAPS>
-hipError_t cluster_passes_tw(int skip, bool sized, int n_tiles, int n_scans, PassLaunch* out);
+int cluster_passes_tw(int skip, bool sized, int n_tiles, PassLaunch* out);
 
 
 

@@ -1,6 +1,7 @@
 // flic_kernels.hip -- gfx950 kernels for FLIC range-image clustering.
 //
-// Three passes over a batch of scans, each scan cut into tiles of
+// Three passes (four kernels with a size threshold) over a batch of scans,
+// each scan cut into tiles of
 // tile_h rows x tile_w columns (tile_h * tile_w = kTilePx, tile_w a multiple
 // of the 64-lane wavefront):
 //
@@ -15,8 +16,10 @@
 //            wavefront ballot.
 //     runs   the k = 1 horizontal ballot gives the row runs directly; a run
 //            whose head has a direct vertical edge takes the strip root above
-//            it as parent (a register and one lane shuffle), so every pixel's
-//            parent is its strip root.
+//            it as parent, any other head starts a new strip root; the head
+//            puts the root in its run's slot (run number from mbcnt) and the
+//            run's lanes read it back, so every pixel's parent is its strip
+//            root.
 //     joins  only edges that may join two different trees go through an LDS
 //            union-find (atomicMin hooking of the larger root under the
 //            smaller): an edge is implied when the same edge one pixel to the
@@ -26,14 +29,18 @@
 //            compressed to their final roots.
 //     output the chunk's run and measurement masks, the tile-local root of
 //            each run (compact run array), and the range and root of every
-//            border slot.  No per-pixel label is written yet.
-//   k_scan_merge   one workgroup per scan: enters the border slots' roots
-//            into an LDS node table, tests the edges between tiles (tile
-//            columns including the 360-degree seam, tile rows) from the
-//            compact border arrays, prunes implied ones and joins the rest in
-//            an LDS union-find, then writes every border slot's final root
-//            over its range.  A root only ever hooks under a smaller one, so
-//            a component's final root is its minimum linear index.
+//            border slot; every border root becomes its own parent in the
+//            scan's parent array.  No per-pixel label is written yet.
+//   k_border_unite one workgroup per tile, one wavefront per 64-pixel chunk
+//            of its right column border (the last tile of a row borders the
+//            first: the 360-degree seam) and lower row border: tests the
+//            crossing edges from the compact border arrays, prunes implied
+//            ones and joins the rest in the scan's union-find in device
+//            memory.  A root only ever hooks under a smaller one, so a
+//            component's final root is its minimum linear index.
+//   k_border_final (size threshold only) one workgroup per tile: writes each
+//            border slot's final root over its range and moves the pixel
+//            count of every non-final border root to its final root.
 //   k_relabel      one workgroup per tile: maps the tile's changed border
 //            roots to final roots in LDS and expands the run roots into the
 //            final labels, one coalesced store per pixel.
@@ -592,11 +599,13 @@ void k_tile_label(BatchRef ref) {
     // Output 2: range and global root of the border columns (and rows), one
     // thread per border slot, contiguous along the border.  The slot index is
     // the offset within the tile's block; a slot outside the image part of the
-    // tile gets (NaN, -1).
+    // tile gets (NaN, -1).  Every border root becomes its own parent in the
+    // scan's parent array, for the joins of pass 2.
     const gptr<float> bcol_v = global(d.bcol_v) + (unsigned)(tile * kColItems);
     const gptr<int> bcol_r = global(d.bcol_r) + (unsigned)(tile * kColItems);
     const gptr<float> brow_v = global(d.brow_v) + (unsigned)(tile * kRowItems);
     const gptr<int> brow_r = global(d.brow_r) + (unsigned)(tile * kRowItems);
+    const gptr<int> gpar = global(d.parent);
 #pragma unroll
     for (int u = 0; u < kSlotRounds; ++u) {
         const int it = threadIdx.x + u * kLabelThreads;
@@ -609,6 +618,7 @@ void k_tile_label(BatchRef ref) {
         if (measured) {
             const unsigned root = par[p];                // strip root -> final root
             groot = base + (root / TW) * W + (root % TW);
+            gpar[(unsigned)groot] = groot;
         }
         if (it < kColItems) {
             bcol_v[it] = slot_v[u];
@@ -631,416 +641,262 @@ void k_tile_label(BatchRef ref) {
     }
 }
 
-// ---- pass 2: edges between tiles, one workgroup per scan ------------------
+// ---- pass 2: edges between tiles --------------------------------------------
 //
-// The nodes are the tile roots that appear in the scan's border slots.  Each
-// is entered into an LDS hash table (key: its global index; the table
-// position is the node), the crossing edges join nodes in an LDS union-find
-// whose root is always the node with the smallest key, and every border slot
-// then gets the key of its node's root -- the minimum linear index of its
-// component -- written over its range.  A scan whose border roots do not fit
-// the table takes the same steps on the scan's parent array in global memory
-// (workgroup-scope atomics: only this workgroup touches it), with an LDS hash
-// set dropping repeated root pairs.
+// One workgroup per tile, one wavefront per item of the tile's outgoing
+// borders: each 64-row chunk of its right column border (the last tile of a
+// tile row borders the first: the 360-degree seam) and, with several tile
+// rows, each 64-column chunk of its lower row border.  The wavefront tests
+// the crossing edges (Eq. 4) between the border slots of the two sides and
+// joins the tile roots at their ends in the scan's union-find over global
+// indices: the parent array in device memory, where pass 1 made every border
+// root its own parent.  A join hooks the larger root under the smaller, so
+// every tree's root is the smallest linear index of its component; the
+// relabel (or, with a size threshold, the finalize pass) reads it.
 //
 // Border values and roots come from the compact arrays written by pass 1;
 // lane = row along a tile column border, lane = column along a tile row
 // border.  An edge is skipped when the same edge one row up (one column
 // left) exists and both its ends continue into this edge's ends by a direct
-// edge inside their tiles.
+// edge inside their tiles: its ends are joined through that edge already.
 
-constexpr int kMergeThreads = 1024;
-constexpr int kSlotBatch = 8;                 // border-slot loads in flight per thread
-constexpr int kNodeBits = 13;
-constexpr int kNodeCap = 1 << kNodeBits;      // LDS node table (global root -> node)
-constexpr int kNodeProbe = 64;
-constexpr int kNoKey = -1;
-constexpr int kSetCap = 8192;                 // global path: LDS hash set of (root, root) pairs
-constexpr int kMaxProbe = 32;
-constexpr unsigned long long kEmpty = ~0ull;
+constexpr int kUniteThreads = 256;
 
-__device__ __forceinline__ int wg_load(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// Joins in the scan's parent array, by workgroups all over the device:
+// device-scope loads (another workgroup's join may have changed an entry,
+// and such loads bypass the per-CU cache) and atomics.
+__device__ __forceinline__ int dev_load(const gptr<int> par, int x) {
+    return __hip_atomic_load(&par[(unsigned)x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Find with path halving: each visited node is re-pointed at its
-// grandparent.  atomicMin keeps this safe next to concurrent hooks: a parent
-// only ever moves to an ancestor (a smaller index in the same tree).
-__device__ __forceinline__ int wg_find(int* par, int x) {
-    int p = wg_load(&par[x]);
+// Find with path halving, as lds_find, on the scan's parent array.
+__device__ __forceinline__ int dev_find(const gptr<int> par, int x) {
+    int p = dev_load(par, x);
     while (p != x) {
-        const int g = wg_load(&par[p]);
+        const int g = dev_load(par, p);
         if (g == p) return p;
-        __hip_atomic_fetch_min(&par[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_min(&par[(unsigned)x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         x = g;
-        p = wg_load(&par[x]);
+        p = dev_load(par, x);
     }
     return x;
 }
 
-__device__ void wg_unite(int* par, int a, int b) {
+// Join, as lds_unite: the larger root goes under the smaller (atomicMin on
+// the larger root's entry); when that entry was no longer a root, the value
+// it held is joined next.  Every retry lowers the larger of the two, so a
+// join always ends.
+__device__ void dev_unite(const gptr<int> par, int a, int b) {
     for (;;) {
-        a = wg_find(par, a);
-        b = wg_find(par, b);
+        a = dev_find(par, a);
+        b = dev_find(par, b);
         if (a == b) return;
-        if (a > b) { int t = a; a = b; b = t; }
-        const int old = __hip_atomic_fetch_min(&par[b], a, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (a > b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = __hip_atomic_fetch_min(&par[(unsigned)b], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == b) return;
         b = old;
     }
 }
 
-// Insert the (a, b) root pairs of the active lanes into the LDS hash set
-// (open addressing, 64-bit compare-and-swap), so each distinct pair is joined
-// once.  A pair that finds no slot within kMaxProbe probes is joined at once.
-__device__ __forceinline__ void push_pairs(bool act, int a, int b, unsigned long long* set,
-                                           int* par, int* overflow) {
-    if (!act) return;
-    const unsigned long long key = ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
-    unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 40) & (kSetCap - 1);
-    for (int probe = 0; probe < kMaxProbe; ++probe) {
-        const unsigned long long old = atomicCAS(&set[h], kEmpty, key);
-        if (old == kEmpty || old == key) return;
-        h = (h + 1) & (kSetCap - 1);
-    }
-    wg_unite(par, a, b);
-    *overflow = 1;
-}
-
-// Enter the (a, b) root pair of an active lane into the LDS hash set; false
-// when it finds no slot within kMaxProbe probes.
-__device__ __forceinline__ bool set_insert(unsigned long long* set, int a, int b) {
-    const unsigned long long key = ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
-    unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 40) & (kSetCap - 1);
-    for (int probe = 0; probe < kMaxProbe; ++probe) {
-        const unsigned long long old = atomicCAS(&set[h], kEmpty, key);
-        if (old == kEmpty || old == key) return true;
-        h = (h + 1) & (kSetCap - 1);
-    }
-    return false;
-}
-
-// ---- LDS node table and union-find over its positions ----
-
-__device__ __forceinline__ unsigned node_hash(int key) {
-    return ((unsigned)key * 2654435761u) >> (32 - kNodeBits);
-}
-
-// Enter a global root; its node, or -1 when no position is free within
-// kNodeProbe probes.
-__device__ __forceinline__ int node_insert(int* keys, int key) {
-    unsigned h = node_hash(key);
-    for (int p = 0; p < kNodeProbe; ++p) {
-        const int old = atomicCAS(&keys[h], kNoKey, key);
-        if (old == kNoKey || old == key) return (int)h;
-        h = (h + 1) & (kNodeCap - 1);
-    }
-    return -1;
-}
-
-// Node of a root that was entered (bounded scan of the probe sequence).
-__device__ __forceinline__ int node_of(const int* keys, int key) {
-    unsigned h = node_hash(key);
-    for (int p = 0; p < kNodeProbe && lds_load(&keys[h]) != key; ++p) h = (h + 1) & (kNodeCap - 1);
-    return (int)h;
-}
-
-// Find with path halving.  A non-root entry only ever moves to an ancestor,
-// and hooks change only roots, so the halving stores need no atomics.
-__device__ __forceinline__ int node_find(int* npar, int x) {
-    int p = lds_load(&npar[x]);
+// The root of x once every join is done (a read-only walk, in a later kernel).
+__device__ __forceinline__ int final_root(const int* par, int x) {
+    int p = par[x];
     while (p != x) {
-        const int g = lds_load(&npar[p]);
-        if (g == p) return p;
-        npar[x] = g;
-        x = g;
-        p = lds_load(&npar[x]);
+        x = p;
+        p = par[x];
     }
     return x;
 }
 
-// Join two sets: the root with the larger key is hooked under the other
-// (compare-and-swap on a root), so every set's root holds its smallest key.
-__device__ void node_unite(int* npar, const int* keys, int a, int b) {
-    for (;;) {
-        a = node_find(npar, a);
-        b = node_find(npar, b);
-        if (a == b) return;
-        if (keys[a] > keys[b]) { const int t = a; a = b; b = t; }
-        if (atomicCAS(&npar[b], b, a) == b) return;
-    }
-}
-
-// Every crossing edge between two tiles of the scan that is not implied:
-// on_edge(need, root_a, root_b) is called by every lane of a wavefront, with
-// need set on the lanes that hold such an edge.
+// Crossing edges of chunk rc (64 rows) of tile t's right column border that
+// are not implied: on_edge(need, root_a, root_b) is called by every lane of
+// the wavefront, with need set on the lanes that hold such an edge.
 template <int TW, int N, bool MAPS, typename F>
-__device__ __forceinline__ void for_crossing_edges(const ScanDesc& d, int lane, int wave, F&& on_edge) {
+__device__ __forceinline__ void col_border_item(const ScanDesc& d, int t, int rc, int lane, F&& on_edge) {
     constexpr int TH = kTilePx / TW;
-    constexpr int kWaves = kMergeThreads / 64;
     const int W = d.W, H = d.H;
     const float t2 = d.t2;
-    // tile column borders: item = (tile, 64-row chunk); the tile's last N
-    // columns against the next N columns to its right (mod W)
-    constexpr int RCH = (TH + 63) / 64;
-    const int n_tiles = d.tiles_x * d.tiles_y;
-    for (int it = wave; it < n_tiles * RCH; it += kWaves) {
-        const int t = it / RCH, rc = it % RCH;
-        const int tx = t % d.tiles_x, ty = t / d.tiles_x;
-        const int col_end = min((tx + 1) * TW, W);
-        const int nc = min(N, col_end - tx * TW);
-        const int th = min(TH, H - ty * TH);
-        const int lr = rc * 64 + lane;
-        if (rc * 64 >= th) continue;
-        const bool in = lr < th;
-        const int row = ty * TH + lr;
-        const size_t src_side = ((size_t)t * 2 + 1) * N * TH;
-        float vs[N], vt[N];
-        int rsrc[N], rtgt[N];
+    const int tx = t % d.tiles_x, ty = t / d.tiles_x;
+    const int col_end = min((tx + 1) * TW, W);
+    const int nc = min(N, col_end - tx * TW);
+    const int th = min(TH, H - ty * TH);
+    const int lr = rc * 64 + lane;
+    if (rc * 64 >= th) return;
+    const bool in = lr < th;
+    const int row = ty * TH + lr;
+    const size_t src_side = ((size_t)t * 2 + 1) * N * TH;
+    float vs[N], vt[N];
+    int rsrc[N], rtgt[N];
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const bool ok = in && j >= N - nc;
-            vs[j] = ok ? d.bcol_v[src_side + (size_t)j * TH + lr] : __builtin_nanf("");
-            rsrc[j] = ok ? d.bcol_r[src_side + (size_t)j * TH + lr] : -1;
-            int q = col_end + j;
-            if (q >= W) q -= W;
-            const int u = q / TW, o = q - u * TW;
-            const size_t tgt_side = ((size_t)(ty * d.tiles_x + u) * 2 + 0) * N * TH;
-            vt[j] = in ? d.bcol_v[tgt_side + (size_t)o * TH + lr] : __builtin_nanf("");
-            rtgt[j] = in ? d.bcol_r[tgt_side + (size_t)o * TH + lr] : -1;
-        }
-        // every table value the item needs, loaded before any data-dependent work
-        float c2h[N][N];
-#pragma unroll
-        for (int j = 0; j < N; ++j)
-#pragma unroll
-            for (int k = 1; k <= N; ++k)
-                c2h[j][k - 1] = (j >= N - nc && j + k >= N)
-                                    ? 2.0f * d.cos_h[(size_t)(k - 1) * W + col_end - N + j] : 0.0f;
-        // direct vertical edges from row - 1 (same tile row, lane > 0)
-        const bool up_ok = lane > 0 && in;
-        const float cv = up_ok ? 2.0f * d.cos_v[row - 1] : 0.0f;
-        bool us[N], ut[N];
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            us[j] = up_ok && connected(__shfl_up(vs[j], 1), vs[j], cv, t2);
-            ut[j] = up_ok && connected(__shfl_up(vt[j], 1), vt[j], cv, t2);
-        }
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            if (j < N - nc) continue;
-#pragma unroll
-            for (int k = 1; k <= N; ++k) {
-                const int m = j + k - N;                 // target slot
-                if (m < 0) continue;
-                bool on = true;                          // MAPS: the left end on the stride-k map
-                if constexpr (MAPS)
-                    if (k >= 2) on = row % k == 0 && (col_end - N + j) % k == 0;
-                const bool e = on && connected(vs[j], vt[m], c2h[j][k - 1], t2);
-                const uint64_t E = ballot(e);
-                const uint64_t V = ballot(us[j] && ut[m]);
-                const bool need = lane_bit(E & ~((E << 1) & V));
-                on_edge(need, rsrc[j], rtgt[m]);
-            }
-        }
+    for (int j = 0; j < N; ++j) {
+        const bool ok = in && j >= N - nc;
+        vs[j] = ok ? d.bcol_v[src_side + (size_t)j * TH + lr] : __builtin_nanf("");
+        rsrc[j] = ok ? d.bcol_r[src_side + (size_t)j * TH + lr] : -1;
+        int q = col_end + j;
+        if (q >= W) q -= W;
+        const int u = q / TW, o = q - u * TW;
+        const size_t tgt_side = ((size_t)(ty * d.tiles_x + u) * 2 + 0) * N * TH;
+        vt[j] = in ? d.bcol_v[tgt_side + (size_t)o * TH + lr] : __builtin_nanf("");
+        rtgt[j] = in ? d.bcol_r[tgt_side + (size_t)o * TH + lr] : -1;
     }
-
-    // tile row borders (only with several tile rows): item = (tile above,
-    // 64-column chunk); its last N rows against the next N rows below
-    if (d.tiles_y > 1) {
-        constexpr int CCH = TW / 64;
-        const int n_upper = d.tiles_x * (d.tiles_y - 1);
-        for (int it = wave; it < n_upper * CCH; it += kWaves) {
-            const int t = it / CCH, cc = it % CCH;
-            const int tx = t % d.tiles_x, ty = t / d.tiles_x;
-            const int tw = min(TW, W - tx * TW);
-            const int lc = cc * 64 + lane;
-            if (cc * 64 >= tw) continue;
-            const bool in = lc < tw;
-            const int col = tx * TW + lc;
-            const int row_end = (ty + 1) * TH;
-            const size_t src_side = ((size_t)t * 2 + 1) * N * TW;
-            const size_t tgt_side = ((size_t)((ty + 1) * d.tiles_x + tx) * 2 + 0) * N * TW;
-            float vs[N], vt[N];
-            int rsrc[N], rtgt[N];
+    // every table value the item needs, loaded before any data-dependent work
+    float c2h[N][N];
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-                vs[j] = in ? d.brow_v[src_side + (size_t)j * TW + lc] : __builtin_nanf("");
-                rsrc[j] = in ? d.brow_r[src_side + (size_t)j * TW + lc] : -1;
-                const bool tok = in && row_end + j < H;
-                vt[j] = tok ? d.brow_v[tgt_side + (size_t)j * TW + lc] : __builtin_nanf("");
-                rtgt[j] = tok ? d.brow_r[tgt_side + (size_t)j * TW + lc] : -1;
-            }
-            float c2v[N][N];
+    for (int j = 0; j < N; ++j)
 #pragma unroll
-            for (int j = 0; j < N; ++j)
+        for (int k = 1; k <= N; ++k)
+            c2h[j][k - 1] = (j >= N - nc && j + k >= N)
+                                ? 2.0f * d.cos_h[(size_t)(k - 1) * W + col_end - N + j] : 0.0f;
+    // direct vertical edges from row - 1 (same tile row, lane > 0)
+    const bool up_ok = lane > 0 && in;
+    const float cv = up_ok ? 2.0f * d.cos_v[row - 1] : 0.0f;
+    bool us[N], ut[N];
 #pragma unroll
-                for (int k = 1; k <= N; ++k)
-                    c2v[j][k - 1] = (j + k >= N && row_end + j + k - N < H)
-                                        ? 2.0f * d.cos_v[(size_t)(k - 1) * H + row_end - N + j] : 0.0f;
-            const bool left_ok = lane > 0 && in;
-            const float chh = left_ok ? 2.0f * d.cos_h[col - 1] : 0.0f;
-            bool ls[N], lt[N];
+    for (int j = 0; j < N; ++j) {
+        us[j] = up_ok && connected(__shfl_up(vs[j], 1), vs[j], cv, t2);
+        ut[j] = up_ok && connected(__shfl_up(vt[j], 1), vt[j], cv, t2);
+    }
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-                ls[j] = left_ok && connected(__shfl_up(vs[j], 1), vs[j], chh, t2);
-                lt[j] = left_ok && connected(__shfl_up(vt[j], 1), vt[j], chh, t2);
-            }
+    for (int j = 0; j < N; ++j) {
+        if (j < N - nc) continue;
 #pragma unroll
-            for (int j = 0; j < N; ++j) {
-#pragma unroll
-                for (int k = 1; k <= N; ++k) {
-                    const int m = j + k - N;
-                    if (m < 0 || row_end + m >= H) continue;
-                    bool on = true;                      // MAPS: the upper end on the stride-k map
-                    if constexpr (MAPS)
-                        if (k >= 2) on = (row_end - N + j) % k == 0 && col % k == 0;
-                    const bool e = on && connected(vs[j], vt[m], c2v[j][k - 1], t2);
-                    const uint64_t E = ballot(e);
-                    const uint64_t L = ballot(ls[j] && lt[m]);
-                    const bool need = lane_bit(E & ~((E << 1) & L));
-                    on_edge(need, rsrc[j], rtgt[m]);
-                }
-            }
+        for (int k = 1; k <= N; ++k) {
+            const int m = j + k - N;                 // target slot
+            if (m < 0) continue;
+            bool on = true;                          // MAPS: the left end on the stride-k map
+            if constexpr (MAPS)
+                if (k >= 2) on = row % k == 0 && (col_end - N + j) % k == 0;
+            const bool e = on && connected(vs[j], vt[m], c2h[j][k - 1], t2);
+            const uint64_t E = ballot(e);
+            const uint64_t V = ballot(us[j] && ut[m]);
+            const bool need = lane_bit(E & ~((E << 1) & V));
+            on_edge(need, rsrc[j], rtgt[m]);
         }
     }
 }
 
-// Root of border slot i of the scan (column slots first, then row slots).
-__device__ __forceinline__ int slot_root(const ScanDesc& d, int i, int n_col) {
-    return i < n_col ? d.bcol_r[i] : d.brow_r[i - n_col];
-}
-
-__device__ __forceinline__ void set_slot_final(const ScanDesc& d, int i, int n_col, int f) {
-    if (i < n_col)
-        reinterpret_cast<int*>(d.bcol_v)[i] = f;
-    else
-        reinterpret_cast<int*>(d.brow_v)[i - n_col] = f;
-}
-
-// SIZE: after the joins, the pixel count of every border root that is not
-// its component's final root is added to the final root's count, so the
-// count array holds every component's size at its final root.
-template <int TW, int N, bool SIZE, bool MAPS>
-__global__ __launch_bounds__(kMergeThreads) void k_scan_merge(BatchRef ref) {
+// The same for chunk cc (64 columns) of the lower row border of tile t (a
+// tile with another tile below it).
+template <int TW, int N, bool MAPS, typename F>
+__device__ __forceinline__ void row_border_item(const ScanDesc& d, int t, int cc, int lane, F&& on_edge) {
     constexpr int TH = kTilePx / TW;
-    __shared__ int keys[kNodeCap];             // node -> global root (kNoKey: free)
-    __shared__ int npar[kNodeCap];             // union-find over nodes
-    __shared__ unsigned long long set[kSetCap];
-    __shared__ int overflow;
+    const int W = d.W, H = d.H;
+    const float t2 = d.t2;
+    const int tx = t % d.tiles_x, ty = t / d.tiles_x;
+    const int tw = min(TW, W - tx * TW);
+    const int lc = cc * 64 + lane;
+    if (cc * 64 >= tw) return;
+    const bool in = lc < tw;
+    const int col = tx * TW + lc;
+    const int row_end = (ty + 1) * TH;
+    const size_t src_side = ((size_t)t * 2 + 1) * N * TW;
+    const size_t tgt_side = ((size_t)((ty + 1) * d.tiles_x + tx) * 2 + 0) * N * TW;
+    float vs[N], vt[N];
+    int rsrc[N], rtgt[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        vs[j] = in ? d.brow_v[src_side + (size_t)j * TW + lc] : __builtin_nanf("");
+        rsrc[j] = in ? d.brow_r[src_side + (size_t)j * TW + lc] : -1;
+        const bool tok = in && row_end + j < H;
+        vt[j] = tok ? d.brow_v[tgt_side + (size_t)j * TW + lc] : __builtin_nanf("");
+        rtgt[j] = tok ? d.brow_r[tgt_side + (size_t)j * TW + lc] : -1;
+    }
+    float c2v[N][N];
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int k = 1; k <= N; ++k)
+            c2v[j][k - 1] = (j + k >= N && row_end + j + k - N < H)
+                                ? 2.0f * d.cos_v[(size_t)(k - 1) * H + row_end - N + j] : 0.0f;
+    const bool left_ok = lane > 0 && in;
+    const float chh = left_ok ? 2.0f * d.cos_h[col - 1] : 0.0f;
+    bool ls[N], lt[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        ls[j] = left_ok && connected(__shfl_up(vs[j], 1), vs[j], chh, t2);
+        lt[j] = left_ok && connected(__shfl_up(vt[j], 1), vt[j], chh, t2);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int k = 1; k <= N; ++k) {
+            const int m = j + k - N;
+            if (m < 0 || row_end + m >= H) continue;
+            bool on = true;                      // MAPS: the upper end on the stride-k map
+            if constexpr (MAPS)
+                if (k >= 2) on = (row_end - N + j) % k == 0 && col % k == 0;
+            const bool e = on && connected(vs[j], vt[m], c2v[j][k - 1], t2);
+            const uint64_t E = ballot(e);
+            const uint64_t L = ballot(ls[j] && lt[m]);
+            const bool need = lane_bit(E & ~((E << 1) & L));
+            on_edge(need, rsrc[j], rtgt[m]);
+        }
+    }
+}
 
-    const ScanDesc d = ref.descs ? ref.descs[blockIdx.x] : ref.one;
+template <int TW, int N, bool MAPS>
+__global__ __launch_bounds__(kUniteThreads) void k_border_unite(BatchRef ref) {
+    constexpr int TH = kTilePx / TW;
+    constexpr int RCH = (TH + 63) / 64, CCH = TW / 64;
+    ScanDesc d;
+    int tile;
+    locate(ref, blockIdx.x, d, tile);
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const int n_tiles = d.tiles_x * d.tiles_y;
-    const int n_col = n_tiles * 2 * N * TH;
-    const int n_slots = n_col + (d.tiles_y > 1 ? n_tiles * 2 * N * TW : 0);
-    for (int i = threadIdx.x; i < kNodeCap; i += kMergeThreads) {
-        keys[i] = kNoKey;
-        npar[i] = i;
+    const int n_items = RCH + (tile / d.tiles_x + 1 < d.tiles_y ? CCH : 0);
+    const gptr<int> par = global(d.parent);
+    // A lane's edges mostly join the same two roots (the columns or rows on
+    // either side belong to the same components), and each join is a chain
+    // of device-scope round trips: a lane joins a root pair only when it
+    // differs from its previous one, and the last pair at the end.
+    int pa = -1, pb = -1;
+    auto join = [&](bool need, int a, int b) {
+        if (need && a != b && (a != pa || b != pb)) {
+            if (pa >= 0) dev_unite(par, pa, pb);
+            pa = a;
+            pb = b;
+        }
+    };
+    for (int it = wave; it < n_items; it += kUniteThreads / 64) {
+        if (it < RCH)
+            col_border_item<TW, N, MAPS>(d, tile, it, lane, join);
+        else
+            row_border_item<TW, N, MAPS>(d, tile, it - RCH, lane, join);
     }
-    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) set[i] = kEmpty;
-    if (threadIdx.x == 0) overflow = 0;
-    __syncthreads();
+    if (pa >= 0) dev_unite(par, pa, pb);
+}
 
-    // every border root becomes a node (kSlotBatch slot loads in flight per
-    // thread); every needed crossing edge becomes a distinct root pair
-    for (int i0 = threadIdx.x; i0 < n_slots; i0 += kSlotBatch * kMergeThreads) {
-        int r[kSlotBatch];
-#pragma unroll
-        for (int u = 0; u < kSlotBatch; ++u) {
-            const int i = i0 + u * kMergeThreads;
-            r[u] = i < n_slots ? slot_root(d, i, n_col) : -1;
-        }
-        // consecutive slots (rows of one border column) mostly share a root:
-        // only the first lane of each run of equal roots enters it
-#pragma unroll
-        for (int u = 0; u < kSlotBatch; ++u) {
-            const int prev = __shfl_up(r[u], 1);
-            if (r[u] >= 0 && (lane == 0 || prev != r[u]) && node_insert(keys, r[u]) < 0) overflow = 1;
-        }
-    }
-    for_crossing_edges<TW, N, MAPS>(d, lane, wave, [&](bool need, int a, int b) {
-        if (need && !set_insert(set, a, b)) overflow = 1;
-    });
-    __syncthreads();
-
-    if (!overflow) {
-        for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) {
-            const unsigned long long key = set[i];
-            if (key != kEmpty)
-                node_unite(npar, keys, node_of(keys, (int)(key >> 32)), node_of(keys, (int)(key & 0xffffffffu)));
-        }
-        __syncthreads();
-        for (int i0 = threadIdx.x; i0 < n_slots; i0 += kSlotBatch * kMergeThreads) {
-            int r[kSlotBatch];
-#pragma unroll
-            for (int u = 0; u < kSlotBatch; ++u) {
-                const int i = i0 + u * kMergeThreads;
-                r[u] = i < n_slots ? slot_root(d, i, n_col) : -1;
-            }
-#pragma unroll
-            for (int u = 0; u < kSlotBatch; ++u)
-                if (r[u] >= 0)
-                    set_slot_final(d, i0 + u * kMergeThreads, n_col, keys[node_find(npar, node_of(keys, r[u]))]);
-        }
-        if constexpr (SIZE) {
-            // one node per border root; a non-final root's count is read
-            // only here (only final roots receive additions)
-            for (int i = threadIdx.x; i < kNodeCap; i += kMergeThreads) {
-                const int k = keys[i];
-                if (k == kNoKey) continue;
-                const int f = keys[node_find(npar, i)];
-                if (f != k) atomicAdd(&d.counts[f], d.counts[k]);
-            }
-        }
-        return;
-    }
-
-    // Too many border roots or root pairs for LDS: the parent array in global
-    // memory.  Every border root starts as its own parent; repeated pairs are
-    // dropped by the set, and a pair that finds no slot is joined at once.
-    int* par = d.parent;
-    __syncthreads();                                 // everyone has read the flag
-    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) set[i] = kEmpty;
-    for (int i = threadIdx.x; i < n_slots; i += kMergeThreads) {
-        const int r = slot_root(d, i, n_col);
-        if (r >= 0) par[r] = r;
-    }
-    if (threadIdx.x == 0) overflow = 0;
-    __syncthreads();
-    for_crossing_edges<TW, N, MAPS>(d, lane, wave, [&](bool need, int a, int b) {
-        push_pairs(need, a, b, set, par, &overflow);
-    });
-    __syncthreads();
-    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) {
-        const unsigned long long key = set[i];
-        if (key != kEmpty) wg_unite(par, (int)(key >> 32), (int)(key & 0xffffffffu));
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kSetCap; i += kMergeThreads) {
-        const unsigned long long key = set[i];
-        if (key == kEmpty) continue;
-        const int a = (int)(key >> 32), b = (int)(key & 0xffffffffu);
-        const int ra = wg_find(par, a);              // a and b now share this root
-        if (ra != a) par[a] = ra;
-        if (ra != b) par[b] = ra;
-    }
-    __syncthreads();
-    // After the compression a root's parent is final, unless a pair was
-    // joined outside the set.
-    const bool walk = overflow != 0;
-    for (int i = threadIdx.x; i < n_slots; i += kMergeThreads) {
-        const int r = slot_root(d, i, n_col);
+// Size threshold only: every border slot's final root is written over its
+// range (for the relabel), and the pixel count of every border root that is
+// not its component's final root moves to the final root (all of a root's
+// slots lie in its own tile; the first to take the count moves it), so the
+// count array holds every component's size at its final root.
+template <int TW, int N>
+__global__ __launch_bounds__(kUniteThreads) void k_border_final(BatchRef ref) {
+    constexpr int TH = kTilePx / TW;
+    constexpr int kColItems = 2 * N * TH, kRowItems = 2 * N * TW;
+    ScanDesc d;
+    int tile;
+    locate(ref, blockIdx.x, d, tile);
+    const int n_slots = kColItems + (d.tiles_y > 1 ? kRowItems : 0);
+    const gptr<const int> bcol_r = global(static_cast<const int*>(d.bcol_r)) + (unsigned)(tile * kColItems);
+    const gptr<const int> brow_r = global(static_cast<const int*>(d.brow_r)) + (unsigned)(tile * kRowItems);
+    const gptr<int> bcol_f = global(reinterpret_cast<int*>(d.bcol_v)) + (unsigned)(tile * kColItems);
+    const gptr<int> brow_f = global(reinterpret_cast<int*>(d.brow_v)) + (unsigned)(tile * kRowItems);
+    for (int i = threadIdx.x; i < n_slots; i += kUniteThreads) {
+        const int r = i < kColItems ? bcol_r[i] : brow_r[i - kColItems];
         if (r < 0) continue;
-        const int f = walk ? wg_find(par, r) : wg_load(&par[r]);
-        set_slot_final(d, i, n_col, f);
-        if constexpr (SIZE) {
-            // a root has many slots: the first to take its count moves it
-            if (f != r) {
-                const int v = atomicExch(&d.counts[r], 0);
-                if (v != 0) atomicAdd(&d.counts[f], v);
-            }
+        const int f = final_root(d.parent, r);
+        if (i < kColItems)
+            bcol_f[i] = f;
+        else
+            brow_f[i - kColItems] = f;
+        if (f != r) {
+            const int v = atomicExch(&d.counts[r], 0);
+            if (v != 0) atomicAdd(&d.counts[f], v);
         }
     }
 }
@@ -1102,12 +958,15 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
     const unsigned ra = (lane >> 3) < rows ? runs[mrow * (kRunHead / 2) + lane] : 0;
     const unsigned rb = 8 + (lane >> 3) < rows ? runs[mrow * (kRunHead / 2) + 64 + lane] : 0;
     const int n_col = 2 * d.N * TH, n_row = d.tiles_y > 1 ? 2 * d.N * TW : 0;
-    // border slots: provisional root and (written by pass 2 over the range)
-    // final root
+    // border slots: provisional root and final root (the root of its tree
+    // in the scan's parent array once pass 2 is done; with a size threshold,
+    // the finalize pass wrote it over the slot's range)
     const gptr<const int> bcol_r = global(static_cast<const int*>(d.bcol_r)) + (unsigned)(tile * n_col);
     const gptr<const int> brow_r = global(static_cast<const int*>(d.brow_r)) + (unsigned)(tile * 2 * d.N * TW);
-    const gptr<const int> bcol_f = global(reinterpret_cast<const int*>(d.bcol_v)) + (unsigned)(tile * n_col);
-    const gptr<const int> brow_f = global(reinterpret_cast<const int*>(d.brow_v)) + (unsigned)(tile * 2 * d.N * TW);
+    [[maybe_unused]] const gptr<const int> bcol_f =
+        global(reinterpret_cast<const int*>(d.bcol_v)) + (unsigned)(tile * n_col);
+    [[maybe_unused]] const gptr<const int> brow_f =
+        global(reinterpret_cast<const int*>(d.brow_v)) + (unsigned)(tile * 2 * d.N * TW);
     constexpr int kSlotRounds = (2 * kMaxSkip * (TH + TW) + kRelabelThreads - 1) / kRelabelThreads;
     int sroot[kSlotRounds], sfin[kSlotRounds];
 #pragma unroll
@@ -1115,7 +974,11 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
         const int it = threadIdx.x + u * kRelabelThreads;
         const bool col = it < n_col, row = !col && it < n_col + n_row;
         sroot[u] = col ? bcol_r[it] : (row ? brow_r[it - n_col] : -1);
-        sfin[u] = col ? bcol_f[it] : (row ? brow_f[it - n_col] : -1);
+        if constexpr (SIZE) sfin[u] = col ? bcol_f[it] : (row ? brow_f[it - n_col] : -1);
+    }
+    if constexpr (!SIZE) {
+#pragma unroll
+        for (int u = 0; u < kSlotRounds; ++u) sfin[u] = sroot[u] >= 0 ? final_root(d.parent, sroot[u]) : -1;
     }
     // border roots that changed -> the LDS map (every slot of a root writes
     // the same value)
@@ -1173,11 +1036,13 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
 
 template <int TW, int N, bool SIZE, bool MAPS>
 hipError_t launch_twn(const BatchRef& ref, int n_tiles, int n_scans, hipStream_t stream, hipEvent_t* ev) {
+    (void)n_scans;
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_tile_label<TW, N, SIZE, MAPS>), dim3(n_tiles), dim3(kLabelThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[1], stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_scan_merge<TW, N, SIZE, MAPS>), dim3(n_scans), dim3(kMergeThreads), 0, stream, ref);
+    hipLaunchKernelGGL((k_border_unite<TW, N, MAPS>), dim3(n_tiles), dim3(kUniteThreads), 0, stream, ref);
+    if (SIZE) hipLaunchKernelGGL((k_border_final<TW, N>), dim3(n_tiles), dim3(kUniteThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[2], stream)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_relabel<TW, SIZE>), dim3(n_tiles), dim3(kRelabelThreads), 0, stream, ref);
     if (ev && (e = hipEventRecord(ev[3], stream)) != hipSuccess) return e;
@@ -1185,26 +1050,31 @@ hipError_t launch_twn(const BatchRef& ref, int n_tiles, int n_scans, hipStream_t
 }
 
 template <int TW, int N, bool SIZE, bool MAPS>
-void passes_twn(int n_tiles, int n_scans, PassLaunch* out) {
-    out[0] = {reinterpret_cast<const void*>(&k_tile_label<TW, N, SIZE, MAPS>), (unsigned)n_tiles,
-              (unsigned)kLabelThreads};
-    out[1] = {reinterpret_cast<const void*>(&k_scan_merge<TW, N, SIZE, MAPS>), (unsigned)n_scans,
-              (unsigned)kMergeThreads};
-    out[2] = {reinterpret_cast<const void*>(&k_relabel<TW, SIZE>), (unsigned)n_tiles, (unsigned)kRelabelThreads};
+int passes_twn(int n_tiles, PassLaunch* out) {
+    int n = 0;
+    out[n++] = {reinterpret_cast<const void*>(&k_tile_label<TW, N, SIZE, MAPS>), (unsigned)n_tiles,
+                (unsigned)kLabelThreads};
+    out[n++] = {reinterpret_cast<const void*>(&k_border_unite<TW, N, MAPS>), (unsigned)n_tiles,
+                (unsigned)kUniteThreads};
+    if (SIZE)
+        out[n++] = {reinterpret_cast<const void*>(&k_border_final<TW, N>), (unsigned)n_tiles,
+                    (unsigned)kUniteThreads};
+    out[n++] = {reinterpret_cast<const void*>(&k_relabel<TW, SIZE>), (unsigned)n_tiles, (unsigned)kRelabelThreads};
+    return n;
 }
 
 template <int TW, bool SIZE, bool MAPS>
-hipError_t passes_tws(int skip, int n_tiles, int n_scans, PassLaunch* out) {
+int passes_tws(int skip, int n_tiles, PassLaunch* out) {
     switch (skip) {
-        case 1: passes_twn<TW, 1, SIZE, false>(n_tiles, n_scans, out); return hipSuccess;
-        case 2: passes_twn<TW, 2, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
-        case 3: passes_twn<TW, 3, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
-        case 4: passes_twn<TW, 4, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
-        case 5: passes_twn<TW, 5, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
-        case 6: passes_twn<TW, 6, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
-        case 7: passes_twn<TW, 7, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
-        case 8: passes_twn<TW, 8, SIZE, MAPS>(n_tiles, n_scans, out); return hipSuccess;
-        default: return hipErrorInvalidValue;
+        case 1: return passes_twn<TW, 1, SIZE, false>(n_tiles, out);
+        case 2: return passes_twn<TW, 2, SIZE, MAPS>(n_tiles, out);
+        case 3: return passes_twn<TW, 3, SIZE, MAPS>(n_tiles, out);
+        case 4: return passes_twn<TW, 4, SIZE, MAPS>(n_tiles, out);
+        case 5: return passes_twn<TW, 5, SIZE, MAPS>(n_tiles, out);
+        case 6: return passes_twn<TW, 6, SIZE, MAPS>(n_tiles, out);
+        case 7: return passes_twn<TW, 7, SIZE, MAPS>(n_tiles, out);
+        case 8: return passes_twn<TW, 8, SIZE, MAPS>(n_tiles, out);
+        default: return 0;
     }
 }
 
@@ -1236,14 +1106,13 @@ hipError_t launch_cluster_tw(const BatchRef& ref, int skip, bool sized, int n_ti
 }
 
 template <int TW, bool MAPS>
-hipError_t cluster_passes_tw(int skip, bool sized, int n_tiles, int n_scans, PassLaunch* out) {
-    return sized ? passes_tws<TW, true, MAPS>(skip, n_tiles, n_scans, out)
-                 : passes_tws<TW, false, MAPS>(skip, n_tiles, n_scans, out);
+int cluster_passes_tw(int skip, bool sized, int n_tiles, PassLaunch* out) {
+    return sized ? passes_tws<TW, true, MAPS>(skip, n_tiles, out) : passes_tws<TW, false, MAPS>(skip, n_tiles, out);
 }
 
 #define FLIC_INSTANTIATE(TW, MAPS) \
     template hipError_t launch_cluster_tw<TW, MAPS>(const BatchRef&, int, bool, int, int, hipStream_t, hipEvent_t*); \
-    template hipError_t cluster_passes_tw<TW, MAPS>(int, bool, int, int, PassLaunch*);
+    template int cluster_passes_tw<TW, MAPS>(int, bool, int, PassLaunch*);
 #if !defined(FLIC_MAPS) || FLIC_MAPS == 0
 #if !defined(FLIC_TILE_W) || FLIC_TILE_W == 64
 FLIC_INSTANTIATE(64, false)

@@ -200,9 +200,8 @@ def _border_pairs_scan(H=128, W=16384, N=3, seg=4, tile_w=64):
     """Every even row holds a short segment across every tile-column border
     (and the 360-degree seam), each row at its own range 1 m from the next, so
     no vertical or skip edge joins two rows: about (H/2) * (W/tile_w) distinct
-    pairs of tile roots meet in the scan merge, twice its 8192-entry pair set,
-    and the pairs that find no slot take the direct join (and the final-root
-    walk that follows it)."""
+    pairs of tile roots (16384) are joined by the border pass, every border
+    item holding many independent joins."""
     img = np.zeros((H, W), np.float32)
     for r in range(0, H, 2):
         for b in range(0, W, tile_w):
@@ -213,19 +212,19 @@ def _border_pairs_scan(H=128, W=16384, N=3, seg=4, tile_w=64):
     return synth.Scan(img, cos_v, cos_h, 0.5, N, None, 0)
 
 
-def test_merge_pair_set_overflow(flic):
+def test_many_border_components(flic):
     scan = _border_pairs_scan()
     want = oracle.cluster_scan(scan)
     # every segment is one component spanning two tiles
     assert len(np.unique(want[want >= 0])) == (scan.range_img.shape[0] // 2) * (scan.range_img.shape[1] // 64)
-    assert_same(run_gpu(flic, scan, tile_w=64), want, "pair-set overflow")
+    assert_same(run_gpu(flic, scan, tile_w=64), want, "many border components")
     ctx = flic.Context(0)
     ctx.set_tile_width(64)
     d = flic.to_device(scan)
     plan = ctx.plan([d])
     plan.relaunch()
     torch.cuda.synchronize()
-    assert_same(d.labels.cpu().numpy(), want, "pair-set overflow, plan")
+    assert_same(d.labels.cpu().numpy(), want, "many border components, plan")
     plan.close()
 
 

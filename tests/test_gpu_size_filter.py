@@ -2,7 +2,7 @@
 for bit, through the C ABI: the counting kernels at every tile width, ragged
 shapes, the hand-derived example, mixed batches (scans with and without a
 threshold), the full 64 x 128x2048 batch at the paper's 100 points, plans
-whose min_points change between launches, the merge's global-memory path,
+whose min_points change between launches, thousands of two-tile components,
 repeated runs, and the degenerate thresholds."""
 import numpy as np
 import pytest
@@ -166,8 +166,7 @@ def _border_pairs_scan(H=128, W=16384, N=3, seg=4, tile_w=64):
     """Every even row holds a 2*seg-pixel segment across every tile-column
     border (and the 360-degree seam), each row at its own range, so about
     (H/2) * (W/tile_w) components of exactly 2*seg pixels, seg in each of two
-    tiles: more root pairs than the merge's LDS set holds, so it takes its
-    global-memory path, where the two halves' counts must be summed."""
+    tiles, whose two halves' counts the border passes must sum."""
     img = np.zeros((H, W), np.float32)
     for r in range(0, H, 2):
         for b in range(0, W, tile_w):
@@ -178,11 +177,11 @@ def _border_pairs_scan(H=128, W=16384, N=3, seg=4, tile_w=64):
     return synth.Scan(img, cos_v, cos_h, 0.5, N, None, 0)
 
 
-def test_merge_global_path_sums_counts(flic):
+def test_border_components_sum_counts(flic):
     scan = _border_pairs_scan()
     lab = oracle.cluster_scan(scan)
     ctx = flic.Context(0)
     for m in (5, 8, 9):        # each half has 4 pixels; only the summed 8 reaches 5 and 8
         want = oracle.filter_small(lab, m)
         assert (want >= 0).any() == (m <= 8)
-        assert_same(run_gpu(flic, scan, m, ctx, tile_w=64), want, f"global merge m={m}")
+        assert_same(run_gpu(flic, scan, m, ctx, tile_w=64), want, f"border components m={m}")

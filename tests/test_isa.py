@@ -34,7 +34,7 @@ def asm(tmp_path_factory):
 def test_no_float_fma_or_packed_fp32(asm):
     for path in asm:
         text = open(path).read()
-        assert "k_tile_label" in text and "k_scan_merge" in text and "k_relabel" in text
+        assert "k_tile_label" in text and "k_border_unite" in text and "k_relabel" in text
         hits = sorted(set(FLOAT_FUSED.findall(text)))
         assert not hits, f"{os.path.basename(path)}: {hits}"
 
