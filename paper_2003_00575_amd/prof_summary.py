@@ -31,7 +31,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "flic_kernels.hip")
 GROUND_SOURCE = os.path.join(HERE, "csrc", "flic_ground.hip")
 COPY_BYTES = 128 << 20          # the calibration copy: 128 MiB read, 128 MiB written
-PASSES = (("tile_label", "k_tile_label"), ("border_merge", "k_border_unite"), ("relabel", "k_relabel"),
+PASSES = (("tile_label", "k_tile_label"), ("border_merge", "k_border_unite"), ("border_final", "k_border_final"),
+          ("relabel", "k_relabel"),
           ("ground", "k_ground"))
 
 
