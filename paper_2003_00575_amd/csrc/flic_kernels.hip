@@ -849,12 +849,20 @@ __global__ __launch_bounds__(kUniteThreads) void k_border_unite(BatchRef ref) {
     const int n_items = RCH + (tile / d.tiles_x + 1 < d.tiles_y ? CCH : 0);
     const gptr<int> par = global(d.parent);
     // A lane's edges mostly join the same two roots (the columns or rows on
-    // either side belong to the same components), and each join is a chain
-    // of device-scope round trips: a lane joins a root pair only when it
-    // differs from its previous one, and the last pair at the end.
+    // either side belong to the same components), and so do the lanes of a
+    // chunk (its rows or columns); each join is a chain of device-scope round
+    // trips, and joins of one pair contend for the same entries.  At each
+    // edge offset a lane skips its pair when the nearest lower lane with an
+    // edge there holds the same pair, and it joins a pair only when it
+    // differs from its own previous one (the last pair at the end).
+    const uint64_t lower_lanes = (1ull << lane) - 1ull;
     int pa = -1, pb = -1;
     auto join = [&](bool need, int a, int b) {
-        if (need && a != b && (a != pa || b != pb)) {
+        const uint64_t lower = ballot(need) & lower_lanes;
+        const int src = lower ? 63 - __clzll(lower) : lane;
+        const int qa = __builtin_amdgcn_ds_bpermute(src << 2, a), qb = __builtin_amdgcn_ds_bpermute(src << 2, b);
+        const bool dup = lower != 0 && qa == a && qb == b;
+        if (need && !dup && a != b && (a != pa || b != pb)) {
             if (pa >= 0) dev_unite(par, pa, pb);
             pa = a;
             pb = b;
@@ -871,21 +879,46 @@ __global__ __launch_bounds__(kUniteThreads) void k_border_unite(BatchRef ref) {
 
 // Size threshold only: every border slot's final root is written over its
 // range (for the relabel), and the pixel count of every border root that is
-// not its component's final root moves to the final root (all of a root's
-// slots lie in its own tile; the first to take the count moves it), so the
-// count array holds every component's size at its final root.
+// not its component's final root moves to the final root, so the count array
+// holds every component's size at its final root.  All of a root's slots lie
+// in its own tile, and a non-final root's count is read by no one else, so
+// the workgroup takes each such root once, through an LDS set of the roots it
+// has seen (one global atomic add per distinct root); a root the set has no
+// room for falls back to an atomic exchange of its count.
+constexpr int kFinalSetBits = 13;
+constexpr int kFinalSet = 1 << kFinalSetBits;       // >= the border slots of a tile (at most 4608)
+constexpr int kFinalProbe = 32;
+
+// True for the first caller with this root, false for every later one;
+// -1 when the probe window is full (then no caller ever inserts the root).
+__device__ __forceinline__ int first_sight(int* set, int key) {
+    unsigned h = ((unsigned)key * 2654435761u) >> (32 - kFinalSetBits);
+    for (int p = 0; p < kFinalProbe; ++p) {
+        const int old = atomicCAS(&set[h], -1, key);
+        if (old == -1) return 1;
+        if (old == key) return 0;
+        h = (h + 1) & (kFinalSet - 1);
+    }
+    return -1;
+}
+
 template <int TW, int N>
 __global__ __launch_bounds__(kUniteThreads) void k_border_final(BatchRef ref) {
     constexpr int TH = kTilePx / TW;
     constexpr int kColItems = 2 * N * TH, kRowItems = 2 * N * TW;
+    static_assert(kColItems + kRowItems <= kFinalSet, "a tile's border roots fit the set");
+    __shared__ int seen[kFinalSet];
     ScanDesc d;
     int tile;
     locate(ref, blockIdx.x, d, tile);
+    for (int i = threadIdx.x; i < kFinalSet; i += kUniteThreads) seen[i] = -1;
+    __syncthreads();
     const int n_slots = kColItems + (d.tiles_y > 1 ? kRowItems : 0);
     const gptr<const int> bcol_r = global(static_cast<const int*>(d.bcol_r)) + (unsigned)(tile * kColItems);
     const gptr<const int> brow_r = global(static_cast<const int*>(d.brow_r)) + (unsigned)(tile * kRowItems);
     const gptr<int> bcol_f = global(reinterpret_cast<int*>(d.bcol_v)) + (unsigned)(tile * kColItems);
     const gptr<int> brow_f = global(reinterpret_cast<int*>(d.brow_v)) + (unsigned)(tile * kRowItems);
+    const gptr<int> counts = global(d.counts);
     for (int i = threadIdx.x; i < n_slots; i += kUniteThreads) {
         const int r = i < kColItems ? bcol_r[i] : brow_r[i - kColItems];
         if (r < 0) continue;
@@ -894,10 +927,13 @@ __global__ __launch_bounds__(kUniteThreads) void k_border_final(BatchRef ref) {
             bcol_f[i] = f;
         else
             brow_f[i - kColItems] = f;
-        if (f != r) {
-            const int v = atomicExch(&d.counts[r], 0);
-            if (v != 0) atomicAdd(&d.counts[f], v);
-        }
+        if (f == r) continue;
+        const int first = first_sight(seen, r);
+        if (first == 0) continue;
+        const int v = first > 0 ? counts[(unsigned)r]
+                                : __hip_atomic_exchange(&counts[(unsigned)r], 0, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        if (v != 0) __hip_atomic_fetch_add(&counts[(unsigned)f], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -994,42 +1030,51 @@ __global__ __launch_bounds__(kRelabelThreads) void k_relabel(BatchRef ref) {
 
     // ... then, row by row: every pixel's run root (from the run array, or
     // for runs beyond the first kRunHead of a chunk from its label segment)
-    // and its final root, one store per pixel
-    [[maybe_unused]] int outs[kRelabelRows];
-#pragma unroll
-    for (int j = 0; j < kRelabelRows; ++j) {
-        const gptr<int> row = global(d.labels) + ((size_t)(r0 + R0 + j) * W + c0 + ch * 64);   // scalar base
+    // and its final root, one store per pixel.  Row j of the strip starts at
+    // labels[strip0 + j * W] (a 32-bit offset: below H * W for every row in
+    // the image).
+    const gptr<int> labels = global(d.labels);
+    const unsigned strip0 = (unsigned)((r0 + R0) * W + c0 + ch * 64);
+    auto row_ptr = [&](int j) __attribute__((always_inline)) { return labels + (strip0 + (unsigned)(j * W)); };
+    auto row_label = [&](int j) __attribute__((always_inline)) -> int {
         const uint64_t starts = lane_word(mine.x, j), valid = lane_word(mine.y, j);
         // run index: starts at or below this lane, minus one
-        const int run = __builtin_amdgcn_mbcnt_hi((unsigned)(starts >> 32),
-                            __builtin_amdgcn_mbcnt_lo((unsigned)starts, lane_bit(starts) ? 0u : ~0u));
+        const int run = count_below(starts, lane_bit(starts) ? 0u : ~0u);
         const unsigned pair = __builtin_amdgcn_ds_bpermute(
             (((j % 8) * 8 + ((run >> 1) & 7)) << 2), (int)(j < 8 ? ra : rb));
         unsigned local = (pair >> ((run & 1) << 4)) & 0xffffu;
-        if (__popcll(starts) > kRunHead) {           // rare: a chunk with many runs
-            const int n = __popcll(starts);
-            const int more = (lane >= kRunHead && lane < n) ? row[lane] : 0;
+        const int n_runs = __popc((unsigned)starts) + __popc((unsigned)(starts >> 32));
+        if (n_runs > kRunHead) {                     // rare: a chunk with many runs
+            const int more = (lane >= kRunHead && lane < n_runs) ? row_ptr(j)[lane] : 0;
             const unsigned far = (unsigned)__builtin_amdgcn_ds_bpermute((run & 63) << 2, more);
             if (run >= kRunHead) local = far;
         }
         local &= kTilePx - 1;
-        const int f = fin[local];
-        const int out = lane_bit(valid) ? (f >= 0 ? f : (int)(base + (local / TW) * W + (local % TW))) : -1;
-        if constexpr (SIZE)
-            outs[j] = out;
-        else if (j < rows && col_in)
-            row[lane] = out;
-    }
+        const int f = fin[local];                    // (read for every lane; selected below)
+        const int own = (int)(base + (local / TW) * W + (local % TW));
+        // -1 for a missing pixel, as a bit operation (no branch around the read)
+        return (f >= 0 ? f : own) | -(int)!lane_bit(valid);
+    };
     if constexpr (SIZE) {
+        int outs[kRelabelRows];
+#pragma unroll
+        for (int j = 0; j < kRelabelRows; ++j) outs[j] = row_label(j);
         const gptr<const int> counts = global(static_cast<const int*>(d.counts));
         const int m = d.min_points;
         int n[kRelabelRows];
 #pragma unroll
         for (int j = 0; j < kRelabelRows; ++j) n[j] = outs[j] >= 0 ? counts[(unsigned)outs[j]] : 0;
 #pragma unroll
+        for (int j = 0; j < kRelabelRows; ++j)
+            if (j < rows && col_in) row_ptr(j)[lane] = n[j] >= m ? outs[j] : -1;
+    } else if (rows == kRelabelRows && ch * 64 + 64 <= tw) {   // (wave-uniform) a whole strip
+#pragma unroll
+        for (int j = 0; j < kRelabelRows; ++j) row_ptr(j)[lane] = row_label(j);
+    } else {
+#pragma unroll
         for (int j = 0; j < kRelabelRows; ++j) {
-            const gptr<int> row = global(d.labels) + ((size_t)(r0 + R0 + j) * W + c0 + ch * 64);
-            if (j < rows && col_in) row[lane] = n[j] >= m ? outs[j] : -1;
+            const int out = row_label(j);
+            if (j < rows && col_in) row_ptr(j)[lane] = out;
         }
     }
 }
