@@ -1,13 +1,15 @@
 """Serving loop: many simulated Lidar sensors, continuous batching on one GPU.
 
 Every sensor registers once: its angle tables and a small pool of frame slots
-(device range + label buffers, pinned host staging) stay resident, admitted
-against an HBM budget.  Frames arrive on their own schedule (Poisson arrivals
-at each sensor's rate).  A frame is admitted as soon as one of its sensor's
+(device range + label buffers, pinned host label buffers) stay resident,
+admitted against an HBM budget.  Frames arrive on their own schedule (Poisson
+arrivals at each sensor's rate) in pinned host receive buffers, as a sensor
+driver delivers them (here: a pinned pool of frames per sensor).  A frame is admitted as soon as one of its sensor's
 slots is free (otherwise it waits, FIFO per sensor); whenever one of the
 launch streams is idle, every admitted frame not yet launched (oldest first,
 up to max_batch) goes out as one batched launch: host-to-device copies, one
-flic_cluster_batched call, device-to-host copy of the labels, an event.  Work
+flic_cluster_batched call, device-to-host copy of the labels, an event (the
+batch's copies go out as one list call each).  Work
 from different streams overlaps on the device.  Latency is measured from a
 frame's arrival to its labels being on the host.
 
@@ -288,6 +290,9 @@ class GpuBackend:
         self.torch, self.flic = torch, flic
         self.ctx = ctx
         self.frames = frames
+        # the sensors' receive buffers: frames arrive in pinned host memory
+        self.rx = {s: [torch.from_numpy(np.ascontiguousarray(f)).pin_memory() for f in pool]
+                   for s, pool in frames.items()}
         self.tables = tables
         self.batched = batched
         self.keep_labels = keep_labels
@@ -344,32 +349,28 @@ class GpuBackend:
                                  self.flic._Tables(dcv.data_ptr(), dch.data_ptr()),
                                  float(spec.threshold), int(spec.skip_depth), lab_d.data_ptr())
             self.slots[(spec.sensor, k)] = {
-                "range": rng_d, "labels": lab_d, "struct": st,
-                "h_in": torch.empty((spec.H, spec.W), dtype=torch.float32, pin_memory=True),
+                "range": rng_d, "labels": lab_d, "struct": st, "src": None,
                 "h_out": torch.empty((spec.H, spec.W), dtype=torch.int32, pin_memory=True),
                 "frame": -1}
 
     def stage(self, sensor: int, slot: int, frame: int) -> None:
         sl = self.slots[(sensor, slot)]
-        pool = self.frames[sensor]
-        sl["h_in"].numpy()[...] = pool[frame % len(pool)]
+        rx = self.rx[sensor]
+        sl["src"] = rx[frame % len(rx)]        # the receive buffer the frame arrived in
         sl["frame"] = frame
 
     def launch(self, stream: int, items: Sequence[Tuple[int, int]]):
         torch = self.torch
         st = self.streams[stream]
+        slots = [self.slots[key] for key in items]
         with torch.cuda.stream(st):
-            for key in items:
-                sl = self.slots[key]
-                sl["range"].copy_(sl["h_in"], non_blocking=True)
+            torch._foreach_copy_([sl["range"] for sl in slots], [sl["src"] for sl in slots], non_blocking=True)
             if self.batched:
-                self.ctx.cluster_batched_structs([self.slots[k]["struct"] for k in items], st)
+                self.ctx.cluster_batched_structs([sl["struct"] for sl in slots], st)
             else:
-                for key in items:
-                    self.ctx.cluster_struct_async(self.slots[key]["struct"], st)
-            for key in items:
-                sl = self.slots[key]
-                sl["h_out"].copy_(sl["labels"], non_blocking=True)
+                for sl in slots:
+                    self.ctx.cluster_struct_async(sl["struct"], st)
+            torch._foreach_copy_([sl["h_out"] for sl in slots], [sl["labels"] for sl in slots], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
         return (ev, list(items))
