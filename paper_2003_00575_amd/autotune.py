@@ -1,11 +1,16 @@
-"""Tile-shape autotuner.
+"""Launch-shape autotuner.
 
 For each shape class (H, W, skip depth) it times the three tile shapes the
 kernels support (64, 128 or 256 columns per 8192-pixel tile) on a batch of
-synthetic scans of that shape, keeps the fastest, and records the choice in a
-JSON cache keyed by GPU architecture.  Applying the cache installs the
-choices as per-shape tile rules on a context (flic_ctx_set_tile_rule); labels
-never depend on the tile shape, only speed does.
+workload scenes of that shape (raycast objects and dropouts, as the mixed
+batch draws them), by the throughput the serving and batch paths see:
+batched launches of the batch overlapped on several streams, microseconds per
+scan over the whole run.  It keeps the fastest.  It also times a plan of the
+mixed-shape batch at several branch splits (flic_ctx_set_plan_parts: the
+launch sequences per shape group, which decide how the groups' border passes
+overlap) and keeps the fastest.  The choices go to a JSON cache keyed by GPU
+architecture; applying the cache installs them on a context (per-shape tile
+rules, plan parts).  Labels never depend on either choice, only speed does.
 
     python -m paper_2003_00575_amd.autotune --out flic_tiles.json
 """
@@ -17,6 +22,8 @@ import os
 from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
 CANDIDATES: Tuple[int, ...] = (64, 128, 256)
+PLAN_PARTS: Tuple[int, ...] = (1, 2, 4)
+PLAN_KEY = "_plan_parts"              # arch-level entry (not a shape)
 Shape = Tuple[int, int, int]          # (H, W, skip depth)
 
 
@@ -62,15 +69,35 @@ def record(cache: Dict[str, Dict[str, dict]], arch: str, shape: Shape,
     return choice
 
 
+def record_plan_parts(cache: Dict[str, Dict[str, dict]], arch: str, timings: Dict[int, float]) -> int:
+    """Fastest plan split; ties go to fewer parts (fewer launches)."""
+    if not timings:
+        raise ValueError("no timings")
+    choice = min(timings, key=lambda p: (timings[p], p))
+    cache.setdefault(arch, {})[PLAN_KEY] = {
+        "parts": choice, "us_per_plan": {str(k): round(v, 3) for k, v in sorted(timings.items())}}
+    return choice
+
+
 def rules_for(cache: Dict[str, Dict[str, dict]], arch: str) -> List[Tuple[int, int, int, int]]:
-    return [(*parse_key(k), int(v["tile_w"])) for k, v in sorted(cache.get(arch, {}).items())]
+    return [(*parse_key(k), int(v["tile_w"])) for k, v in sorted(cache.get(arch, {}).items())
+            if not k.startswith("_")]
+
+
+def plan_parts_for(cache: Dict[str, Dict[str, dict]], arch: str) -> Optional[int]:
+    entry = cache.get(arch, {}).get(PLAN_KEY)
+    return None if entry is None else int(entry["parts"])
 
 
 def apply(ctx, cache: Dict[str, Dict[str, dict]], arch: str) -> int:
-    """Install the cached choices on a flic Context; returns how many."""
+    """Install the cached choices on a flic Context; returns how many tile
+    rules (the plan split, when cached, is installed too)."""
     rules = rules_for(cache, arch)
     for H, W, N, tw in rules:
         ctx.set_tile_rule(H, W, N, tw)
+    parts = plan_parts_for(cache, arch)
+    if parts is not None:
+        ctx.set_plan_parts(parts)
     return len(rules)
 
 
@@ -87,32 +114,63 @@ def gpu_arch() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
-def time_shape(ctx, shape: Shape, n_scans: int = 32, reps: int = 8,
-               candidates: Sequence[int] = CANDIDATES) -> Dict[int, float]:
-    """Mean microseconds per scan of the three passes, per candidate tile width
-    (batched launches, HIP events around each pass)."""
+def workload_scan(H: int, W: int, N: int, i: int, threshold: float = 0.5):
+    """Scan i of a tuning batch: a raycast scene of this shape drawn as the
+    mixed batch draws its scans (field of view of the matching mixed shape,
+    else the 64-beam one; 40 objects and 10 % i.i.d. dropouts up to 64 rows,
+    120 objects and 20 % bursts above)."""
+    from . import synth
+    top, bot = 2.0, -24.8
+    for h, w, t, b in synth.MIXED_SHAPES:
+        if (h, w) == (H, W):
+            top, bot = t, b
+    if H <= 64:
+        return synth.synth_scan(H, W, top, bot, 40, "iid10", 9000 + i, threshold, N)
+    return synth.synth_scan(H, W, top, bot, 120, "burst20", 9000 + i, threshold, N)
+
+
+def _overlapped_us(launch, streams, reps: int) -> float:
+    """Microseconds of `reps` rounds of launch(k, stream) on every stream,
+    from one event before to one after all of them (stream 0 joins the rest)."""
     import torch
-    from . import flic, synth
+    s0 = streams[0]
+    for k, st in enumerate(streams):                 # warm-up
+        launch(k, st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s0)
+    for st in streams[1:]:
+        st.wait_event(e0)
+    for _ in range(reps):
+        for k, st in enumerate(streams):
+            launch(k, st)
+    for st in streams[1:]:
+        ev = torch.cuda.Event()
+        ev.record(st)
+        s0.wait_event(ev)
+    e1.record(s0)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3
+
+
+def time_shape(ctx, shape: Shape, n_scans: int = 32, reps: int = 8,
+               candidates: Sequence[int] = CANDIDATES, n_streams: int = 3) -> Dict[int, float]:
+    """Microseconds per scan, per candidate tile width, of batched launches of
+    n_scans workload scenes overlapped on n_streams streams (each stream its
+    own copy of the batch)."""
+    import torch
+    from . import flic
     H, W, N = shape
-    scans = []
-    for i in range(n_scans):
-        s = synth.random_scan(H, W, N, seed=9000 + i, threshold=0.5, p_invalid=0.15)
-        scans.append(flic.to_device(s))
-    arr = flic.Context.scan_array(scans)
+    host = [workload_scan(H, W, N, i) for i in range(n_scans)]
+    arrs = [flic.Context.scan_array([flic.to_device(s) for s in host]) for _ in range(n_streams)]
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
     out: Dict[int, float] = {}
     previous = ctx.tile_for(H, W, N)
     try:
         for tw in candidates:
             ctx.set_tile_rule(H, W, N, tw)
-            ctx.cluster_batched_array(arr)            # warm-up (allocates scratch)
-            torch.cuda.synchronize()
-            ctx.set_pass_timing(True)
-            ctx.pass_times()
-            for _ in range(reps):
-                ctx.cluster_batched_array(arr)
-            ms, n = ctx.pass_times()
-            ctx.set_pass_timing(False)
-            out[tw] = sum(ms) / max(1, n) * 1e3 / n_scans
+            us = _overlapped_us(lambda k, st: ctx.cluster_batched_array(arrs[k], st), streams, reps)
+            out[tw] = us / (reps * n_streams * n_scans)
     finally:
         ctx.set_tile_rule(H, W, N, 0)
         if previous != ctx.tile_for(H, W, N):
@@ -120,12 +178,39 @@ def time_shape(ctx, shape: Shape, n_scans: int = 32, reps: int = 8,
     return out
 
 
+def time_plan_parts(ctx, n_scans: int = 64, reps: int = 8, candidates: Sequence[int] = PLAN_PARTS,
+                    n_streams: int = 2) -> Dict[int, float]:
+    """Microseconds per relaunch of a plan over n_scans mixed-shape scans,
+    per plan split, relaunches overlapped on n_streams streams (each stream
+    its own plan over its own copy of the scans)."""
+    import torch
+    from . import flic, synth
+    host = [synth.mixed_scan(i) for i in range(n_scans)]
+    devs = [[flic.to_device(s) for s in host] for _ in range(n_streams)]
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+    out: Dict[int, float] = {}
+    for parts in candidates:
+        ctx.set_plan_parts(parts)
+        plans = [ctx.plan(d) for d in devs]
+        try:
+            us = _overlapped_us(lambda k, st: plans[k].relaunch(st), streams, reps)
+        finally:
+            for p in plans:
+                p.close()
+        out[parts] = us / (reps * n_streams)
+    ctx.set_plan_parts(1)
+    return out
+
+
 def tune(ctx, shapes: Iterable[Shape], cache_path: Optional[str] = None,
-         n_scans: int = 32, reps: int = 8) -> Dict[str, Dict[str, dict]]:
+         n_scans: int = 32, reps: int = 8, plan_scans: int = 64) -> Dict[str, Dict[str, dict]]:
     arch = gpu_arch()
     cache = load_cache(cache_path) if cache_path else {}
     for shape in shapes:
         record(cache, arch, shape, time_shape(ctx, shape, n_scans, reps))
+    apply(ctx, cache, arch)                          # plans time with the tile choices
+    if plan_scans > 0:
+        record_plan_parts(cache, arch, time_plan_parts(ctx, plan_scans, reps))
     if cache_path:
         save_cache(cache_path, cache)
     apply(ctx, cache, arch)
@@ -138,10 +223,12 @@ def main() -> int:
     ap.add_argument("--out", default="flic_tiles.json")
     ap.add_argument("--skip", type=int, default=3)
     ap.add_argument("--scans", type=int, default=32)
+    ap.add_argument("--plan-scans", type=int, default=64,
+                    help="mixed-shape scans in the plan-split timing (0: skip it)")
     args = ap.parse_args()
     shapes = [(H, W, args.skip) for H, W, _, _ in synth.MIXED_SHAPES]
     ctx = flic.Context(0)
-    cache = tune(ctx, shapes, args.out, n_scans=args.scans)
+    cache = tune(ctx, shapes, args.out, n_scans=args.scans, plan_scans=args.plan_scans)
     print(json.dumps(cache, indent=1, sort_keys=True))
     return 0
 

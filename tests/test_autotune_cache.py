@@ -20,3 +20,35 @@ def test_cache_round_trip(tmp_path):
     assert autotune.rules_for(back, "gfx942") == [(16, 1024, 3, 64)]
     assert autotune.parse_key(autotune.shape_key(32, 1800, 5)) == (32, 1800, 5)
     assert autotune.load_cache(str(tmp_path / "missing.json")) == {}
+
+
+class _FakeCtx:
+    def __init__(self):
+        self.rules, self.parts = [], None
+
+    def set_tile_rule(self, H, W, N, tw):
+        self.rules.append((H, W, N, tw))
+
+    def set_plan_parts(self, parts):
+        self.parts = parts
+
+
+def test_plan_parts_entry(tmp_path):
+    cache = {}
+    autotune.record(cache, "gfx950", (128, 2048, 3), {64: 1.0, 128: 1.5, 256: 2.0})
+    # fastest split wins; a tie goes to fewer parts
+    assert autotune.record_plan_parts(cache, "gfx950", {1: 300.0, 2: 280.0, 4: 310.0}) == 2
+    assert autotune.record_plan_parts(cache, "gfx950", {1: 300.0, 2: 300.0, 4: 310.0}) == 1
+    p = str(tmp_path / "t.json")
+    autotune.save_cache(p, cache)
+    back = autotune.load_cache(p)
+    # the arch-level entry is not a shape rule
+    assert autotune.rules_for(back, "gfx950") == [(128, 2048, 3, 64)]
+    assert autotune.plan_parts_for(back, "gfx950") == 1
+    assert autotune.plan_parts_for(back, "gfx942") is None
+    ctx = _FakeCtx()
+    assert autotune.apply(ctx, back, "gfx950") == 1
+    assert ctx.rules == [(128, 2048, 3, 64)] and ctx.parts == 1
+    ctx = _FakeCtx()
+    autotune.apply(ctx, {"gfx950": {"16x1024xN3": {"tile_w": 128}}}, "gfx950")
+    assert ctx.parts is None                     # no entry: the context keeps its split
