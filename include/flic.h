@@ -190,10 +190,10 @@ flic_status flic_ctx_set_tile_rule(flic_ctx* ctx, int32_t H, int32_t W, int32_t 
  * share a launch configuration (tile width, skip depth, size threshold or
  * not, skip-edge mode) into up to `parts` launch sequences over consecutive
  * scans.  Every sequence is its own branch of the plan's graph (different
- * groups are always separate branches), so that one branch's scan merge
- * (one workgroup per scan, latency-bound) overlaps the other branches' tile
- * and relabel passes.  parts 1..64 (1, the default, keeps one sequence per
- * group); labels do not depend on it.  FLIC_EINVAL otherwise.              */
+ * groups are always separate branches), so that the branches' passes can
+ * overlap.  parts 1..64 (1, the default, keeps one sequence per group; on
+ * full-GPU batches more parts only add launches); labels do not depend on
+ * it.  FLIC_EINVAL otherwise.                                              */
 flic_status flic_ctx_set_plan_parts(flic_ctx* ctx, int32_t parts);
 
 /* The tile width the context would use for such a scan.                   */

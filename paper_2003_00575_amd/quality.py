@@ -110,10 +110,19 @@ def _sweep(n_scans: int, thresholds: List[float], depths: List[int], modes=(0,),
     host_rng = rng.cpu().numpy()
     measured_frac = float(((host_rng > 0) & np.isfinite(host_rng)).mean())
     ext = mask.cpu().numpy().astype(bool)
-    print(f"Section III.A removes {ext.mean() / measured_frac:.4f} of the measurements", flush=True)
+    gt_ground = np.stack([s.object_id == 0 for s in scans]) & (host_rng > 0) & np.isfinite(host_rng)
+
+    def mask_iou(m: np.ndarray) -> float:
+        return float((m & gt_ground).sum() / max(1, (m | gt_ground).sum()))
+
+    print(f"Section III.A removes {ext.mean() / measured_frac:.4f} of the measurements "
+          f"(ground truth: {gt_ground.mean() / measured_frac:.4f}); IoU with the true ground "
+          f"{mask_iou(ext):.4f}", flush=True)
     if literal_g5:
         lit = literal_first_channel(host_rng, ext)
-        print(f"... with the literal first-channel rule: {lit.mean() / measured_frac:.4f}", flush=True)
+        print(f"... with the literal first-channel rule: {lit.mean() / measured_frac:.4f}; IoU with the "
+              f"true ground {mask_iou(lit):.4f}; cells the readings differ on: "
+              f"{(lit != ext).mean() / measured_frac:.4f} of the measurements", flush=True)
         lit_img = rng.clone()
         lit_img[torch.from_numpy(lit).to(dev)] = 0.0
         grounds.append(("III.A literal g5", lit_img))
