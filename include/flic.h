@@ -150,6 +150,21 @@ flic_status flic_cluster_noalloc(const float* range_img, int32_t H, int32_t W,
 flic_status flic_cluster_batched(flic_ctx* ctx, const flic_scan* scans,
                                  int32_t n, void* hip_stream);
 
+/* flic_cluster_batched for callers whose data lives in host memory: on
+ * `hip_stream`, each scan's range image is first copied from
+ * host_ranges[i] (H*W float32, row-major) into scans[i].range_img, then the
+ * batch is clustered, then each scan's labels are copied to host_labels[i]
+ * (H*W int32).  host_ranges or host_labels may be null (no copies that way),
+ * and so may single entries.  Host buffers should be pinned (hipHostMalloc)
+ * for the copies to be asynchronous; they must stay valid, and untouched,
+ * until the stream reaches the last copy.  This is the continuous-batching
+ * serving path: one call per batch instead of two copies per frame.
+ * Returns like flic_cluster_batched; on an error in a copy, earlier copies
+ * and launches may already be enqueued.  Section III.B (the same labels).   */
+flic_status flic_cluster_batched_host(flic_ctx* ctx, const flic_scan* scans, int32_t n,
+                                      const float* const* host_ranges, int32_t* const* host_labels,
+                                      void* hip_stream);
+
 /* Build a reusable plan for batches shaped like `scans` (same n, and per
  * entry the same H, W, skip_depth and min_points > 0 or not): descriptors are laid out once on the
  * device, tile shapes come from the autotune table, and the launch sequence

@@ -659,6 +659,32 @@ flic_status flic_cluster_batched(flic_ctx* ctx, const flic_scan* scans, int32_t 
     return FLIC_OK;
 }
 
+flic_status flic_cluster_batched_host(flic_ctx* ctx, const flic_scan* scans, int32_t n,
+                                      const float* const* host_ranges, int32_t* const* host_labels,
+                                      void* hip_stream) {
+    if (!ctx) return fail(FLIC_EINVAL, "ctx is null");
+    flic_status st = check_scans(scans, n);
+    if (st != FLIC_OK) return st;
+    if (n == 0) return FLIC_OK;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(set_device(ctx->device));
+    if (host_ranges)
+        for (int32_t i = 0; i < n; ++i)
+            if (host_ranges[i])
+                HIP_TRY(hipMemcpyAsync(const_cast<float*>(scans[i].range_img), host_ranges[i],
+                                       (size_t)scans[i].H * scans[i].W * sizeof(float), hipMemcpyHostToDevice,
+                                       stream));
+    st = flic_cluster_batched(ctx, scans, n, hip_stream);
+    if (st != FLIC_OK) return st;
+    if (host_labels)
+        for (int32_t i = 0; i < n; ++i)
+            if (host_labels[i])
+                HIP_TRY(hipMemcpyAsync(host_labels[i], scans[i].labels_out,
+                                       (size_t)scans[i].H * scans[i].W * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                       stream));
+    return FLIC_OK;
+}
+
 flic_status flic_plan_create(flic_ctx* ctx, const flic_scan* scans, int32_t n, flic_plan** out) {
     if (!ctx || !out) return fail(FLIC_EINVAL, "null ctx or out");
     if (n < 1) return fail(FLIC_EINVAL, "a plan needs n >= 1");

@@ -74,6 +74,9 @@ def lib() -> ctypes.CDLL:
     L.flic_cluster_noalloc.restype = i32
     L.flic_cluster_batched.argtypes = [vp, ctypes.POINTER(_Scan), i32, vp]
     L.flic_cluster_batched.restype = i32
+    L.flic_cluster_batched_host.argtypes = [vp, ctypes.POINTER(_Scan), i32, ctypes.POINTER(vp),
+                                            ctypes.POINTER(vp), vp]
+    L.flic_cluster_batched_host.restype = i32
     L.flic_plan_create.argtypes = [vp, ctypes.POINTER(_Scan), i32, ctypes.POINTER(vp)]
     L.flic_plan_create.restype = i32
     L.flic_plan_launch.argtypes = [vp, ctypes.POINTER(_Scan), i32, vp]
@@ -267,6 +270,13 @@ class Context:
         """flic_cluster_batched on already marshalled flic_scan structs."""
         arr = (_Scan * max(1, len(structs)))(*structs)
         _check(lib().flic_cluster_batched(self.handle, arr, len(structs), _stream_handle(stream)))
+
+    def cluster_batched_host(self, structs, n: int, host_ranges, host_labels, stream=None) -> None:
+        """flic_cluster_batched_host on marshalled arrays: `structs` a ctypes
+        array of n flic_scan, host_ranges / host_labels ctypes arrays of n
+        host addresses (pinned buffers), or None."""
+        _check(lib().flic_cluster_batched_host(self.handle, structs, n, host_ranges, host_labels,
+                                               _stream_handle(stream)))
 
     def cluster_struct_async(self, sc: _Scan, stream=None) -> None:
         """flic_cluster_async on one marshalled flic_scan struct."""

@@ -7,9 +7,9 @@ arrivals at each sensor's rate) in pinned host receive buffers, as a sensor
 driver delivers them (here: a pinned pool of frames per sensor).  A frame is admitted as soon as one of its sensor's
 slots is free (otherwise it waits, FIFO per sensor); whenever one of the
 launch streams is idle, every admitted frame not yet launched (oldest first,
-up to max_batch) goes out as one batched launch: host-to-device copies, one
-flic_cluster_batched call, device-to-host copy of the labels, an event (the
-batch's copies go out as one list call each).  Work
+up to max_batch) goes out as one flic_cluster_batched_host call (each frame's
+host-to-device copy, the batched launch, each frame's labels back to pinned
+host memory) and an event.  Work
 from different streams overlaps on the device.  Latency is measured from a
 frame's arrival to its labels being on the host.
 
@@ -348,31 +348,38 @@ class GpuBackend:
             st = self.flic._Scan(rng_d.data_ptr(), spec.H, spec.W,
                                  self.flic._Tables(dcv.data_ptr(), dch.data_ptr()),
                                  float(spec.threshold), int(spec.skip_depth), lab_d.data_ptr())
+            h_out = torch.empty((spec.H, spec.W), dtype=torch.int32, pin_memory=True)
             self.slots[(spec.sensor, k)] = {
-                "range": rng_d, "labels": lab_d, "struct": st, "src": None,
-                "h_out": torch.empty((spec.H, spec.W), dtype=torch.int32, pin_memory=True),
-                "frame": -1}
+                "range": rng_d, "labels": lab_d, "struct": st, "src": 0,
+                "h_out": h_out, "out": h_out.data_ptr(), "frame": -1}
 
     def stage(self, sensor: int, slot: int, frame: int) -> None:
         sl = self.slots[(sensor, slot)]
         rx = self.rx[sensor]
-        sl["src"] = rx[frame % len(rx)]        # the receive buffer the frame arrived in
+        sl["src"] = rx[frame % len(rx)].data_ptr()   # the receive buffer the frame arrived in
         sl["frame"] = frame
 
     def launch(self, stream: int, items: Sequence[Tuple[int, int]]):
+        import ctypes
         torch = self.torch
         st = self.streams[stream]
         slots = [self.slots[key] for key in items]
-        with torch.cuda.stream(st):
-            torch._foreach_copy_([sl["range"] for sl in slots], [sl["src"] for sl in slots], non_blocking=True)
-            if self.batched:
-                self.ctx.cluster_batched_structs([sl["struct"] for sl in slots], st)
-            else:
-                for sl in slots:
-                    self.ctx.cluster_struct_async(sl["struct"], st)
-            torch._foreach_copy_([sl["h_out"] for sl in slots], [sl["labels"] for sl in slots], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(st)
+        n = len(slots)
+        structs = (self.flic._Scan * n)(*[sl["struct"] for sl in slots])
+        h_in = (ctypes.c_void_p * n)(*[sl["src"] for sl in slots])
+        h_out = (ctypes.c_void_p * n)(*[sl["out"] for sl in slots])
+        if self.batched:
+            self.ctx.cluster_batched_host(structs, n, h_in, h_out, st)
+        else:                                 # one launch sequence (and its copies) per frame
+            size = ctypes.sizeof(self.flic._Scan)
+            vp = ctypes.sizeof(ctypes.c_void_p)
+            for i in range(n):
+                self.ctx.cluster_batched_host(
+                    ctypes.cast(ctypes.addressof(structs) + i * size, ctypes.POINTER(self.flic._Scan)), 1,
+                    ctypes.cast(ctypes.addressof(h_in) + i * vp, ctypes.POINTER(ctypes.c_void_p)),
+                    ctypes.cast(ctypes.addressof(h_out) + i * vp, ctypes.POINTER(ctypes.c_void_p)), st)
+        ev = torch.cuda.Event()
+        ev.record(st)
         return (ev, list(items))
 
     def done(self, token) -> bool:

@@ -119,3 +119,9 @@ def test_noalloc_rejects_before_any_hip_call(L):
 
 def test_plan_parts_validated(L):
     assert L.flic_ctx_set_plan_parts(None, 3) == flic.FLIC_EINVAL
+
+
+def test_batched_host_rejects_null_ctx(L):
+    arr = (flic._Scan * 1)()
+    assert L.flic_cluster_batched_host(None, arr, 1, None, None, None) == flic.FLIC_EINVAL
+    assert "ctx" in flic.last_error()

@@ -269,3 +269,28 @@ def test_plan_parts_as_parallel_branches(flic, parts):
         for i, d in enumerate(devs):
             assert_same(d.labels.cpu().numpy(), want[i], f"parts {parts} rep {rep} scan {i}")
     plan.close()
+
+
+def test_batched_host_copies_in_and_out(flic):
+    """flic_cluster_batched_host: ranges copied in from pinned host buffers,
+    the batch clustered, labels copied out to pinned host buffers, all on one
+    stream; equal to the oracle (mixed shapes), twice on the same buffers with
+    new host data."""
+    import ctypes
+    ctx = flic.Context(0)
+    stream = torch.cuda.Stream()
+    for rep in range(2):
+        scans = [synth.mixed_scan(40 * rep + i) for i in range(10)]
+        devs = [flic.to_device(s) for s in scans]
+        for d in devs:
+            d.range_img.zero_()                   # the data must come from the host copy
+        h_in = [torch.from_numpy(s.range_img).pin_memory() for s in scans]
+        h_out = [torch.full(s.range_img.shape, -7, dtype=torch.int32).pin_memory() for s in scans]
+        arr = flic.Context.scan_array(devs)
+        n = len(devs)
+        hin = (ctypes.c_void_p * n)(*[t.data_ptr() for t in h_in])
+        hout = (ctypes.c_void_p * n)(*[t.data_ptr() for t in h_out])
+        ctx.cluster_batched_host(arr, n, hin, hout, stream)
+        stream.synchronize()
+        for i, s in enumerate(scans):
+            assert_same(h_out[i].numpy(), oracle.cluster_scan(s), f"rep {rep} scan {i}")
