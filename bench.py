@@ -345,6 +345,8 @@ def main() -> int:
                     help="parallel graph branches per launch group in the 256-scan uneven-batch plan")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="host threads of the oracle's all-core leg (0: every core this process may use, at most 16)")
+    ap.add_argument("--tile-table", default=None,
+                    help="autotuner cache to apply instead of the shipped tiles.json")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed batch and the per-kernel timing (for profilers)")
     ap.add_argument("--profile-stress", action="store_true",
@@ -380,7 +382,7 @@ def main() -> int:
     if args.profile_stress:
         from paper_2003_00575_amd import autotune
         ctx = flic.Context(0)
-        autotune.apply_default(ctx)
+        autotune.apply_default(ctx, args.tile_table)
         st = stress_set(ctx, flic, synth, torch, dev, torch.cuda.current_stream(), reps=3)
         print(json.dumps({"profile_stress": True, "labels_mismatching": st["labels_mismatching"],
                           "runs": st["runs"]}), flush=True)
@@ -404,7 +406,7 @@ def main() -> int:
 
     from paper_2003_00575_amd import autotune
     ctx = flic.Context(0)
-    autotune.apply_default(ctx)
+    autotune.apply_default(ctx, args.tile_table)
     if args.tile_w:
         ctx.set_tile_width(args.tile_w)
     ctx.set_plan_parts(args.plan_parts)

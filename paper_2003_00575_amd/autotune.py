@@ -8,9 +8,13 @@ batched launches of the batch overlapped on several streams, microseconds per
 scan over the whole run.  It keeps the fastest.  It also times a plan of the
 mixed-shape batch at several branch splits (flic_ctx_set_plan_parts: the
 launch sequences per shape group, which decide how the groups' border passes
-overlap) and keeps the fastest.  The choices go to a JSON cache keyed by GPU
-architecture; applying the cache installs them on a context (per-shape tile
-rules, plan parts).  Labels never depend on either choice, only speed does.
+overlap) and keeps the fastest.  Last, since scans of different shapes share
+launches (a mixed batch, the serving loop), it refines the per-shape tile
+widths one shape at a time by the relaunch time of one plan over 256
+mixed-shape scans, keeping a change only when it is at least 3 % faster.  The choices go to a
+JSON cache keyed by GPU architecture; applying the cache installs them on a
+context (per-shape tile rules, plan parts).  Labels never depend on either
+choice, only speed does.
 
     python -m paper_2003_00575_amd.autotune --out flic_tiles.json
 """
@@ -104,9 +108,10 @@ def apply(ctx, cache: Dict[str, Dict[str, dict]], arch: str) -> int:
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles.json")
 
 
-def apply_default(ctx) -> int:
-    """Install the shipped tile table for this GPU (if it has an entry)."""
-    return apply(ctx, load_cache(DEFAULT_CACHE), gpu_arch())
+def apply_default(ctx, path: Optional[str] = None) -> int:
+    """Install the shipped tile table (or the one at `path`) for this GPU, if
+    it has an entry."""
+    return apply(ctx, load_cache(path or DEFAULT_CACHE), gpu_arch())
 
 
 def gpu_arch() -> str:
@@ -178,39 +183,81 @@ def time_shape(ctx, shape: Shape, n_scans: int = 32, reps: int = 8,
     return out
 
 
-def time_plan_parts(ctx, n_scans: int = 64, reps: int = 8, candidates: Sequence[int] = PLAN_PARTS,
-                    n_streams: int = 2) -> Dict[int, float]:
-    """Microseconds per relaunch of a plan over n_scans mixed-shape scans,
-    per plan split, relaunches overlapped on n_streams streams (each stream
-    its own plan over its own copy of the scans)."""
-    import torch
-    from . import flic, synth
-    host = [synth.mixed_scan(i) for i in range(n_scans)]
-    devs = [[flic.to_device(s) for s in host] for _ in range(n_streams)]
-    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+class MixedPlanTimer:
+    """Relaunch time of one plan over n_scans mixed-shape scans (the current
+    rules of the context) on one stream: the median over `repeats` timings of
+    `reps` back-to-back relaunches (single timings vary by a few per cent)."""
+
+    def __init__(self, ctx, n_scans: int = 256, reps: int = 20, repeats: int = 5):
+        import torch
+        from . import flic, synth
+        self.ctx, self.reps, self.repeats = ctx, reps, repeats
+        host = [synth.mixed_scan(i) for i in range(n_scans)]
+        self.shapes = sorted({(s.H, s.W, s.skip_depth) for s in host})
+        self.devs = [flic.to_device(s) for s in host]
+        self.stream = torch.cuda.Stream()
+
+    def us_per_plan(self) -> float:
+        plan = self.ctx.plan(self.devs)
+        try:
+            times = sorted(_overlapped_us(lambda k, st: plan.relaunch(st), [self.stream], self.reps) / self.reps
+                           for _ in range(self.repeats))
+        finally:
+            plan.close()
+        return times[len(times) // 2]
+
+
+def time_plan_parts(ctx, n_scans: int = 256, candidates: Sequence[int] = PLAN_PARTS,
+                    timer: Optional[MixedPlanTimer] = None) -> Dict[int, float]:
+    """Microseconds per relaunch of the mixed-shape plan, per plan split."""
+    timer = timer or MixedPlanTimer(ctx, n_scans)
     out: Dict[int, float] = {}
     for parts in candidates:
         ctx.set_plan_parts(parts)
-        plans = [ctx.plan(d) for d in devs]
-        try:
-            us = _overlapped_us(lambda k, st: plans[k].relaunch(st), streams, reps)
-        finally:
-            for p in plans:
-                p.close()
-        out[parts] = us / (reps * n_streams)
+        out[parts] = timer.us_per_plan()
     ctx.set_plan_parts(1)
     return out
 
 
+def refine_in_mix(ctx, cache: Dict[str, Dict[str, dict]], arch: str, timer: MixedPlanTimer,
+                  candidates: Sequence[int] = CANDIDATES, min_gain: float = 0.03) -> float:
+    """Coordinate descent over the tile widths of the mixed plan's shapes:
+    one shape at a time, each other width is tried and kept when the plan
+    relaunches at least min_gain faster.  Updates the cache; returns the
+    final microseconds per plan."""
+    apply(ctx, cache, arch)
+    best = timer.us_per_plan()
+    for H, W, N in timer.shapes:
+        key = shape_key(H, W, N)
+        if key not in cache.get(arch, {}):
+            continue
+        entry = cache[arch][key]
+        plan_us = {str(entry["tile_w"]): round(best, 3)}
+        for tw in candidates:
+            if tw == entry["tile_w"]:
+                continue
+            ctx.set_tile_rule(H, W, N, tw)
+            us = timer.us_per_plan()
+            plan_us[str(tw)] = round(us, 3)
+            if us < best * (1.0 - min_gain):
+                best = us
+                entry["tile_w"] = tw
+        ctx.set_tile_rule(H, W, N, entry["tile_w"])
+        entry["us_per_mixed_plan"] = dict(sorted(plan_us.items()))
+    return best
+
+
 def tune(ctx, shapes: Iterable[Shape], cache_path: Optional[str] = None,
-         n_scans: int = 32, reps: int = 8, plan_scans: int = 64) -> Dict[str, Dict[str, dict]]:
+         n_scans: int = 32, reps: int = 8, plan_scans: int = 256) -> Dict[str, Dict[str, dict]]:
     arch = gpu_arch()
     cache = load_cache(cache_path) if cache_path else {}
     for shape in shapes:
         record(cache, arch, shape, time_shape(ctx, shape, n_scans, reps))
     apply(ctx, cache, arch)                          # plans time with the tile choices
     if plan_scans > 0:
-        record_plan_parts(cache, arch, time_plan_parts(ctx, plan_scans, reps))
+        timer = MixedPlanTimer(ctx, plan_scans)
+        refine_in_mix(ctx, cache, arch, timer)
+        record_plan_parts(cache, arch, time_plan_parts(ctx, timer=timer))
     if cache_path:
         save_cache(cache_path, cache)
     apply(ctx, cache, arch)
@@ -223,7 +270,7 @@ def main() -> int:
     ap.add_argument("--out", default="flic_tiles.json")
     ap.add_argument("--skip", type=int, default=3)
     ap.add_argument("--scans", type=int, default=32)
-    ap.add_argument("--plan-scans", type=int, default=64,
+    ap.add_argument("--plan-scans", type=int, default=256,
                     help="mixed-shape scans in the plan-split timing (0: skip it)")
     args = ap.parse_args()
     shapes = [(H, W, args.skip) for H, W, _, _ in synth.MIXED_SHAPES]

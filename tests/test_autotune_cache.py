@@ -52,3 +52,36 @@ def test_plan_parts_entry(tmp_path):
     ctx = _FakeCtx()
     autotune.apply(ctx, {"gfx950": {"16x1024xN3": {"tile_w": 128}}}, "gfx950")
     assert ctx.parts is None                     # no entry: the context keeps its split
+
+
+class _CostCtx(_FakeCtx):
+    def __init__(self):
+        super().__init__()
+        self.width = {}
+
+    def set_tile_rule(self, H, W, N, tw):
+        self.width[(H, W, N)] = tw
+
+
+class _FakeTimer:
+    """Plan time = 100 + per-shape cost of its tile width (weighted)."""
+    shapes = [(16, 1024, 3), (128, 4096, 3)]
+    cost = {(16, 1024, 3): {64: 3.0, 128: 2.0, 256: 2.03}, (128, 4096, 3): {64: 30.0, 128: 20.0, 256: 25.0}}
+
+    def __init__(self, ctx):
+        self.ctx = ctx
+
+    def us_per_plan(self):
+        return 100.0 + sum(self.cost[s][self.ctx.width.get(s, 64)] for s in self.shapes)
+
+
+def test_refine_in_mix_keeps_only_clear_gains():
+    ctx = _CostCtx()
+    cache = {"gfx950": {"16x1024xN3": {"tile_w": 256}, "128x4096xN3": {"tile_w": 64}}}
+    best = autotune.refine_in_mix(ctx, cache, "gfx950", _FakeTimer(ctx))
+    # 128x4096: 64 -> 128 saves 10 of ~132 (kept); 16x1024: 256 -> 128 saves 0.03 (< 3 %, not kept)
+    assert cache["gfx950"]["128x4096xN3"]["tile_w"] == 128
+    assert cache["gfx950"]["16x1024xN3"]["tile_w"] == 256
+    assert best == 100.0 + 2.03 + 20.0
+    assert set(cache["gfx950"]["128x4096xN3"]["us_per_mixed_plan"]) == {"64", "128", "256"}
+    assert ctx.width[(128, 4096, 3)] == 128
