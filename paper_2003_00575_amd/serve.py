@@ -254,10 +254,14 @@ class ServingCore:
             t0 = min((r.t_arrival for r in self.records), default=0.0)
         kept = [r for r in done if r.t_arrival - t0 >= warmup_s]
         lat = [r.latency * 1e3 for r in kept]
+        # launch -> labels on the host: the device part of a frame's latency
+        # (copies, kernels, completion seen by the loop), without the queueing
+        dev = [(r.t_done - r.t_launch) * 1e3 for r in kept]
         span = (max(r.t_done for r in kept) - min(r.t_arrival for r in kept)) if kept else math.nan
         px = sum(self.specs[r.sensor].H * self.specs[r.sensor].W for r in kept)
         return {"frames": len(kept), "dropped": self.dropped, "batches": self.batches,
                 "p50_ms": order_stat(lat, 0.50), "p99_ms": order_stat(lat, 0.99),
+                "launch_p50_ms": order_stat(dev, 0.50), "launch_p99_ms": order_stat(dev, 0.99),
                 "max_ms": max(lat) if lat else math.nan,
                 "scans_per_s": len(kept) / span if kept and span > 0 else math.nan,
                 "gpix_per_s": px / span / 1e9 if kept and span > 0 else math.nan,
