@@ -94,6 +94,8 @@ using gptr = __attribute__((address_space(1))) T*;
 template <typename T>
 __device__ __forceinline__ gptr<T> global(T* p) { return (gptr<T>)p; }
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) float lds_float;   // LDS pointers (32-bit addresses)
+typedef __attribute__((address_space(3))) int lds_int;
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 // The wavefront's index in its workgroup, as a wave-uniform (scalar) value,
@@ -199,7 +201,7 @@ __device__ void lds_unite(int* par, int a, int b) {
 
 constexpr int kPad = 8;            // >= kMaxSkip
 constexpr int kRowsPerWave = 8;    // kTilePx / 64 / kLabelWaves
-constexpr int kNoRoot = 0xffff;    // "no strip root above" (tile indices are < 8192)
+constexpr int kC2Rows = kRowsPerWave + kMaxSkip;   // vertical 2*cos entries per wavefront and offset
 
 // Eq. (4) with both squares already formed: (sq1 + sq2) - ((2 cos a) * (d1 * d2)).
 // Symmetric in its two ends (IEEE addition and multiplication commute).
@@ -251,10 +253,11 @@ void k_tile_label(BatchRef ref) {
     constexpr int RS = TW + kPad;             // LDS row stride of the ranges
     constexpr int LR = TH + N;                // LDS rows: N NaN rows, then the tile
     static_assert(TH * CH == kLabelWaves * kRowsPerWave, "one 8-row strip per wavefront");
-    static_assert(kTilePx <= kNoRoot, "tile indices fit 16 bits");
+    static_assert(kTilePx <= 0x10000, "tile indices fit 16 bits");
     __shared__ float rs[LR * RS];
     __shared__ int par[kTilePx];
     __shared__ int run_root[kLabelWaves * 65];   // per wavefront: strip root of run k (1..64) of the row
+    __shared__ float c2t[kLabelWaves * N * kC2Rows];   // per wavefront: vertical 2*cos by offset and row
 
     ScanDesc d;
     int tile;
@@ -349,10 +352,19 @@ void k_tile_label(BatchRef ref) {
         c2hk[k] = c < tw ? 2.0f * cosh_l[k] : 0.0f;
         c2vl[k] = (xl >= 0 && xl < th && r0 + xl + k + 1 < H) ? 2.0f * cosv_l[k] : 0.0f;
     }
-    // the (wave-uniform) 2*cos between strip rows R0 - N + l and R0 - N + l + k
-    auto c2v = [&](int k, int l) __attribute__((always_inline)) {
-        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c2vl[k - 1]), l));
-    };
+    // The (wave-uniform) 2*cos between strip rows R0 - N + l and R0 - N + l + k,
+    // from a per-wavefront LDS table: a read of one address by every lane
+    // costs one LDS instruction and no VALU work.
+    // (The table address is kept in a vector register: the reads then need
+    // no copy of a scalar address first.)
+    lds_float* c2w = (lds_float*)(c2t + wave * (N * kC2Rows));
+    if (lane < kC2Rows) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) c2w[k * kC2Rows + lane] = c2vl[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" : "+v"(c2w) :: "memory");             // written by other lanes of this wavefront
+    auto c2v = [&](int k, int l) __attribute__((always_inline)) { return c2w[(k - 1) * kC2Rows + l]; };
 
     // Window of the N rows above the current one: value, square, direct
     // horizontal ballot (h1) and direct vertical ballot to the row above it
@@ -374,23 +386,35 @@ void k_tile_label(BatchRef ref) {
         }
     }
 
-    // Edge ballots row by row (top-down).  todo bit 0: the next pixel across
-    // a strip border; bit k (1..N): k rows up; bit N+k-1 (k >= 2): k columns
-    // right.  A bit is set only when the edge may join two different trees.
-    uint32_t todo[kRowsPerWave];
+    // The current row's ranges and the strip's parents through vector
+    // registers that hold their addresses: every read and write of a row then
+    // has a constant offset (one address add per row for the ranges).
+    lds_float* row_p = (lds_float*)(at + R0 * RS);
+    lds_int* par_p = (lds_int*)(par + R0 * TW + c);
+    asm volatile("" : "+v"(row_p), "+v"(par_p));
+
+    // Edge ballots row by row (top-down).  Join bits of row j (JB bits per
+    // row, packed per lane into todo): bit 0: the next pixel across a strip
+    // border; bit k (1..N): k rows up; bit N+k-1 (k >= 2): k columns right.
+    // A bit is set only when the edge may join two different trees.
+    constexpr int JB = 2 * N <= 8 ? 8 : 16;
+    constexpr int JW = kRowsPerWave * JB / 32;
+    uint32_t todo[JW];
+#pragma unroll
+    for (int w = 0; w < JW; ++w) todo[w] = 0;
     // Per row j, as 32-bit words held by single lanes: lane 4j + q holds word q
     // of the row's (run starts, measurements) mask pair, lane 2j + q word q
     // of its new strip roots (run heads that took no parent above).
     unsigned words = 0, sroot_words = 0;
-    int above = kNoRoot;                                 // strip root of the pixel above
+    int above = 0;                                        // strip root of the pixel above (rows j >= 1)
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
         const int r = R0 + j;
-        const float a = at[r * RS];
+        const float a = row_p[0];
         const float sa = a * a;
-        uint32_t t = 0;
+        uint32_t t = 0;                                   // this row's join bits
         // direct edges (k = 1)
-        const float b1 = at[r * RS + 1];
+        const float b1 = row_p[1];
         const uint64_t h1 = ballot(connected_sq(a, sa, b1, b1 * b1, c2hk[0], t2));
         const uint64_t v1 = ballot(connected_sq(wv[0], ws[0], a, sa, c2v(1, j - 1 + N), t2));
         const uint64_t vmask = ballot(a == a);
@@ -414,7 +438,7 @@ void k_tile_label(BatchRef ref) {
             uint64_t run = h1;
 #pragma unroll
             for (int k = 2; k <= N; ++k) {
-                const float b = at[r * RS + k];
+                const float b = row_p[k];
                 bool on = true;
                 if constexpr (MAPS) on = (r0 + r) % k == 0 && ((col_on_map >> k) & 1u);
                 const uint64_t hk = ballot(on && connected_sq(a, sa, b, b * b, c2hk[k - 1], t2));
@@ -445,20 +469,23 @@ void k_tile_label(BatchRef ref) {
             }
         }
         // Runs: a run head with a (pruned) direct vertical edge takes the
-        // strip root above it, any other head is a new strip root.  Each head
-        // puts its root in its run's slot (run number = heads at or below the
-        // lane, 1-based), and every lane of the run reads it back.
+        // strip root above it, any other head is a new strip root (every head
+        // of the strip's first row: the row above is another strip's).  Each
+        // head puts its root in its run's slot (run number = heads at or
+        // below the lane, 1-based: bit 0 of the mask goes into the scalar
+        // base), and every lane of the run reads it back.
         const uint64_t starts = vmask & ~(h1 << 1);       // heads of the row's runs
-        const bool up = lane_bit(link);
-        const int got = up ? above : kNoRoot;             // read at heads only
-        const int run = count_below(starts >> 1, (unsigned)(starts & 1u));
-        int* slot = run_root + wave * 65 + run;
-        if (lane_bit(starts)) *slot = got != kNoRoot ? got : r * TW + c;
+        const uint64_t took = j == 0 ? 0ull : (starts & link);
+        const uint64_t sroots = starts & ~took;
+        int* slot = run_root + wave * 65 + (int)(starts & 1u) + count_below(starts >> 1);
+        if (lane_bit(starts)) *slot = lane_bit(took) ? above : r * TW + c;
         asm volatile("" ::: "memory");                    // one store, then one load for all lanes
         const int root = *slot;                           // (garbage for a missing pixel: never read)
-        par[r * TW + c] = root;
-        if (up && above != root) t |= 2u;                // may join another tree above
-        const uint64_t sroots = starts & ~ballot(got != kNoRoot);
+        par_p[j * TW] = root;
+        // a direct vertical edge that may join another tree (every one in the
+        // first row: the root above is not known here)
+        const uint64_t join_up = j == 0 ? link : (link & ballot(above != root));
+        if (lane_bit(join_up)) t |= 2u;
         words = write_lane(words, (unsigned)starts, 4 * j + 0);
         words = write_lane(words, (unsigned)(starts >> 32), 4 * j + 1);
         words = write_lane(words, (unsigned)vmask, 4 * j + 2);
@@ -469,8 +496,8 @@ void k_tile_label(BatchRef ref) {
         // materialise this row's per-lane results here: otherwise the compiler
         // sinks them to their uses after the barrier and keeps the 64-bit
         // masks alive (spilled) instead
-        asm volatile("" : "+v"(t), "+v"(words), "+v"(sroot_words), "+v"(above));
-        todo[j] = t;
+        todo[j * JB / 32] |= t << (j * JB % 32);
+        asm volatile("" : "+v"(todo[j * JB / 32]), "+v"(words), "+v"(sroot_words), "+v"(above));
 #pragma unroll
         for (int k = N - 1; k >= 1; --k) {
             wv[k] = wv[k - 1];
@@ -484,6 +511,8 @@ void k_tile_label(BatchRef ref) {
         wh1[0] = h1;
         wv1[0] = v1;
         wvm[0] = vmask;
+        row_p += RS;
+        asm volatile("" : "+v"(row_p));
         // keep rows apart: interleaving them only raises scalar-register pressure
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -492,31 +521,21 @@ void k_tile_label(BatchRef ref) {
     // The range buffer is free now: each wavefront uses its 512-entry slice
     // of it as a queue.  Every pixel's parent is its strip root, and every
     // tree node above a pixel is a strip root.
-    static_assert(kTilePx <= (1 << 13) && 2 * kMaxSkip <= 32 - 13, "queue entry packing");
     static_assert(kLabelWaves * kRowsPerWave * 64 <= LR * RS, "queues fit the range buffer");
     int* queue = reinterpret_cast<int*>(rs) + wave * (kRowsPerWave * 64);
 
-    // Join: the strip's pixels with join bits (index | bits << 13), one lane
-    // per pixel (about three per strip).
-    {
-        int count = 0;
+    // Join: each lane joins the edges of its own column's pixels that carry
+    // join bits (about three per strip).
 #pragma unroll
-        for (int j = 0; j < kRowsPerWave; ++j) {
-            const uint64_t m = ballot(todo[j] != 0);
-            if (todo[j]) queue[count + count_below(m)] = ((R0 + j) * TW + c) | (int)(todo[j] << 13);
-            count += __popcll(m);
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int e = lane; e < count; e += 64) {
-            const int w = queue[e];
-            const int i = w & (kTilePx - 1);
-            uint32_t t = (uint32_t)w >> 13;
-            while (t) {
-                const int b = __builtin_ctz(t);
-                t &= t - 1;
-                const int other = b == 0 ? i + 1 : (b <= N ? i - b * TW : i + (b - N + 1));
-                lds_unite(par, i, other);
-            }
+    for (int w = 0; w < JW; ++w) {
+        uint32_t t = todo[w];
+        while (t) {
+            const int b = __builtin_ctz(t);
+            t &= t - 1;
+            const int j = w * (32 / JB) + b / JB, e = b % JB;
+            const int i = (R0 + j) * TW + c;
+            const int other = e == 0 ? i + 1 : (e <= N ? i - e * TW : i + (e - N + 1));
+            lds_unite(par, i, other);
         }
     }
     __syncthreads();
@@ -578,8 +597,10 @@ void k_tile_label(BatchRef ref) {
         const unsigned root = node[j];
         const int k = count_below(starts);               // run index in the chunk
         // (a row outside the image has no run heads: its ranges are NaN)
-        if (head && k < kRunHead) strip_runs[j * kRunHead + k] = (uint16_t)root;
-        if (__popc((unsigned)starts) + __popc((unsigned)(starts >> 32)) > kRunHead) {   // rare: many runs
+        if (__popcll(starts) <= kRunHead) {
+            if (head) strip_runs[j * kRunHead + k] = (uint16_t)root;
+        } else {                                          // rare: many runs
+            if (head && k < kRunHead) strip_runs[j * kRunHead + k] = (uint16_t)root;
             if (head && k >= kRunHead) (labels + (lbase + j * W))[k] = root;
         }
         if (head) {
