@@ -393,15 +393,10 @@ void k_tile_label(BatchRef ref) {
     lds_int* par_p = (lds_int*)(par + R0 * TW + c);
     asm volatile("" : "+v"(row_p), "+v"(par_p));
 
-    // Edge ballots row by row (top-down).  Join bits of row j (JB bits per
-    // row, packed per lane into todo): bit 0: the next pixel across a strip
-    // border; bit k (1..N): k rows up; bit N+k-1 (k >= 2): k columns right.
-    // A bit is set only when the edge may join two different trees.
-    constexpr int JB = 2 * N <= 8 ? 8 : 16;
-    constexpr int JW = kRowsPerWave * JB / 32;
-    uint32_t todo[JW];
-#pragma unroll
-    for (int w = 0; w < JW; ++w) todo[w] = 0;
+    // Edge ballots row by row (top-down).  todo bit 0: the next pixel across
+    // a strip border; bit k (1..N): k rows up; bit N+k-1 (k >= 2): k columns
+    // right.  A bit is set only when the edge may join two different trees.
+    uint32_t todo[kRowsPerWave];
     // Per row j, as 32-bit words held by single lanes: lane 4j + q holds word q
     // of the row's (run starts, measurements) mask pair, lane 2j + q word q
     // of its new strip roots (run heads that took no parent above).
@@ -496,8 +491,8 @@ void k_tile_label(BatchRef ref) {
         // materialise this row's per-lane results here: otherwise the compiler
         // sinks them to their uses after the barrier and keeps the 64-bit
         // masks alive (spilled) instead
-        todo[j * JB / 32] |= t << (j * JB % 32);
-        asm volatile("" : "+v"(todo[j * JB / 32]), "+v"(words), "+v"(sroot_words), "+v"(above));
+        asm volatile("" : "+v"(t), "+v"(words), "+v"(sroot_words), "+v"(above));
+        todo[j] = t;
 #pragma unroll
         for (int k = N - 1; k >= 1; --k) {
             wv[k] = wv[k - 1];
@@ -524,18 +519,29 @@ void k_tile_label(BatchRef ref) {
     static_assert(kLabelWaves * kRowsPerWave * 64 <= LR * RS, "queues fit the range buffer");
     int* queue = reinterpret_cast<int*>(rs) + wave * (kRowsPerWave * 64);
 
-    // Join: each lane joins the edges of its own column's pixels that carry
-    // join bits (about three per strip).
+    // Join: the strip's pixels with join bits (index | bits << 13), one lane
+    // per pixel (about three per strip; many more where components
+    // interleave, hence a queue rather than each lane taking its own column).
+    static_assert(kTilePx <= (1 << 13) && 2 * kMaxSkip <= 32 - 13, "queue entry packing");
+    {
+        int count = 0;
 #pragma unroll
-    for (int w = 0; w < JW; ++w) {
-        uint32_t t = todo[w];
-        while (t) {
-            const int b = __builtin_ctz(t);
-            t &= t - 1;
-            const int j = w * (32 / JB) + b / JB, e = b % JB;
-            const int i = (R0 + j) * TW + c;
-            const int other = e == 0 ? i + 1 : (e <= N ? i - e * TW : i + (e - N + 1));
-            lds_unite(par, i, other);
+        for (int j = 0; j < kRowsPerWave; ++j) {
+            const uint64_t m = ballot(todo[j] != 0);
+            if (todo[j]) queue[count + count_below(m)] = ((R0 + j) * TW + c) | (int)(todo[j] << 13);
+            count += __popcll(m);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int e = lane; e < count; e += 64) {
+            const int w = queue[e];
+            const int i = w & (kTilePx - 1);
+            uint32_t t = (uint32_t)w >> 13;
+            while (t) {
+                const int b = __builtin_ctz(t);
+                t &= t - 1;
+                const int other = b == 0 ? i + 1 : (b <= N ? i - b * TW : i + (b - N + 1));
+                lds_unite(par, i, other);
+            }
         }
     }
     __syncthreads();
