@@ -283,6 +283,118 @@ flic_status flic_ground_remove(flic_ctx* ctx, const float* range_in, int32_t n_s
                                int32_t H, int32_t W, const flic_ground_tables* tables,
                                float* range_out, uint8_t* ground_mask, void* hip_stream);
 
+/* ---- Serving runtime --------------------------------------------------------
+ * Frames of many sensors clustered continuously on one device, each frame as
+ * it arrives (the real-time, scan-by-scan use of Section IV.A), with the
+ * frames that are ready at the same time sharing one batched launch.
+ *
+ * A server owns per sensor its angle tables and slots_per_sensor device frame
+ * slots (range and label buffers), admitted against hbm_budget together with
+ * the context's launch ring (reserved for max_batch frames of the largest
+ * registered shape).  A submitted frame waits FIFO per sensor; beyond
+ * max_queue waiting frames the oldest is dropped.  It is admitted when one
+ * of its sensor's slots is free.  Whenever one of n_streams launch streams
+ * is idle, every admitted frame not yet launched (oldest first, at most
+ * max_batch) goes out in one flic_cluster_batched_host call on that stream:
+ * each frame's host-to-device copy, one batched launch, each frame's labels
+ * back to its host buffer.  Labels are those of flic_cluster (scan-local
+ * linear indices, Section III.B, no size threshold, dense skip edges).
+ *
+ * Times are seconds on the server's clock (flic_server_now: a monotonic clock
+ * started at creation).  submit and progress take the current time from the
+ * caller, so a driver (or a test) decides when events happen; replay runs a
+ * whole arrival schedule in real time.  A server is used by one thread at a
+ * time.  Host buffers should be pinned (hipHostMalloc) for the copies to be
+ * asynchronous; each must stay valid until its frame is done.
+ *
+ * With ctx == NULL the server simulates the device: nothing is allocated or
+ * launched, and a launch is done sim_launch_s seconds after it was made
+ * (host buffers are then never touched and may be null).                   */
+typedef struct flic_server flic_server;
+
+typedef struct {
+    int32_t n_streams;        /* launch streams, 1..8                            */
+    int32_t max_batch;        /* frames per launch, 1..1024 (1: one launch each) */
+    int32_t slots_per_sensor; /* device frame slots per sensor, 1..16            */
+    int32_t max_queue;        /* waiting frames per sensor before drops, >= 1    */
+    uint64_t hbm_budget;      /* bytes: tables + slots + launch ring; 0 = no cap */
+    double sim_launch_s;      /* simulated launch duration (ctx == NULL), >= 0   */
+} flic_server_config;
+
+/* One frame's history.  batch is the launch's sequence number (-1 when the
+ * frame was dropped or not launched yet); t_done is +inf for a dropped
+ * frame and NaN for one not done yet.                                       */
+typedef struct {
+    int32_t sensor;
+    int32_t batch;
+    int64_t tag;
+    double t_arrival;
+    double t_admit;
+    double t_launch;
+    double t_done;
+} flic_frame_record;
+
+/* One scheduled arrival for flic_server_replay: at t seconds after the
+ * replay starts, a frame of `sensor` arrives in host_range ([H][W] float32)
+ * and its labels go to host_labels ([H][W] int32).                         */
+typedef struct {
+    double t;
+    int32_t sensor;
+    int32_t pad_;
+    const float* host_range;
+    int32_t* host_labels;
+} flic_arrival;
+
+/* Create a server on ctx's device (ctx may be NULL: simulated device).  The
+ * context stays owned by the caller and must outlive the server.
+ * FLIC_EINVAL for a null out-pointer or a config field out of range.       */
+flic_status flic_server_create(flic_ctx* ctx, const flic_server_config* cfg, flic_server** out);
+
+/* Register a sensor of H x W frames with skip depth skip_depth and threshold
+ * (metres); host_tables holds host pointers to the angle tables in the
+ * layout of flic_alpha_tables (copied to the device).  The sensor's id is
+ * written to *sensor_out (0, 1, ... in registration order).  FLIC_EINVAL
+ * for arguments flic_cluster would reject; FLIC_ENOMEM (nothing kept) when
+ * the budget or a device allocation does not allow it.                    */
+flic_status flic_server_add_sensor(flic_server* srv, int32_t H, int32_t W, const flic_alpha_tables* host_tables,
+                                   float threshold, int32_t skip_depth, int32_t* sensor_out);
+
+/* A frame of `sensor` that arrived at t_arrival; `now` is the current time
+ * (its admission time when a slot is free).  tag is returned in its
+ * record.  FLIC_EINVAL for an unknown sensor or (with a device) a null
+ * buffer.                                                                  */
+flic_status flic_server_submit(flic_server* srv, double now, double t_arrival, int32_t sensor,
+                               const float* host_range, int32_t* host_labels, int64_t tag);
+
+/* Retire finished launches (their frames are done at `now`, their slots go
+ * back to the sensors and waiting frames are admitted), then launch on every
+ * idle stream.  *completed (may be null) gets the number of frames retired.
+ * FLIC_EHIP on a failed HIP call; the server must then be destroyed.       */
+flic_status flic_server_progress(flic_server* srv, double now, int32_t* completed);
+
+/* Run n arrivals (t non-decreasing, relative to the start of the replay) in
+ * real time: submit each when its time comes, progress in between, until
+ * every frame is done or dropped.  Records keep the arrival times on the
+ * server clock.                                                             */
+flic_status flic_server_replay(flic_server* srv, const flic_arrival* arrivals, int32_t n);
+
+/* The current time on the server clock.                                    */
+double flic_server_now(const flic_server* srv);
+
+/* Records of the frames submitted since creation or the last clear, in
+ * submission order: writes min(n_max, count) records to out (out may be
+ * null with n_max 0) and the count to *n_out; also the number of dropped
+ * frames and of launches (either may be null).                             */
+flic_status flic_server_records(const flic_server* srv, flic_frame_record* out, int64_t n_max, int64_t* n_out,
+                                int64_t* dropped, int64_t* launches);
+
+/* Forget the records and counters; only while no frame is waiting, admitted
+ * or in flight (FLIC_EINVAL otherwise).                                    */
+flic_status flic_server_clear(flic_server* srv);
+
+/* Wait for the server's streams, then free everything it allocated.       */
+void flic_server_destroy(flic_server* srv);
+
 /* Message for the last error on this thread ("" if none).                  */
 const char* flic_last_error(void);
 

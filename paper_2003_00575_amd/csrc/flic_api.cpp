@@ -841,3 +841,7 @@ void flic_plan_destroy(flic_plan* plan) {
 }
 
 }  // extern "C"
+
+void flic::record_error(const char* msg) { g_last_error = msg; }
+
+int flic::ctx_device(const flic_ctx* ctx) { return ctx->device; }

@@ -160,3 +160,12 @@ constexpr int kMaxDevices = 64;
 hipError_t noalloc_scratch(int device, void** out);
 
 }  // namespace flic
+
+// Shared by the host files: the message flic_last_error returns on this
+// thread, and the device a context was created on.
+struct flic_ctx;
+namespace flic {
+void record_error(const char* msg);
+int ctx_device(const flic_ctx* ctx);
+
+}  // namespace flic

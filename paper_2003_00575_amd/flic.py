@@ -46,6 +46,29 @@ class _GroundTables(ctypes.Structure):
                 ("sensor_height", ctypes.c_float), ("tan_theta", ctypes.c_float)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("slots_per_sensor", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_uint64), ("sim_launch_s", ctypes.c_double)]
+
+
+class _FrameRecord(ctypes.Structure):
+    _fields_ = [("sensor", ctypes.c_int32), ("batch", ctypes.c_int32), ("tag", ctypes.c_int64),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class _Arrival(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("sensor", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("host_range", ctypes.c_void_p), ("host_labels", ctypes.c_void_p)]
+
+
+# numpy views of the record and arrival structs (same layout)
+RECORD_DTYPE = [("sensor", "<i4"), ("batch", "<i4"), ("tag", "<i8"), ("t_arrival", "<f8"),
+                ("t_admit", "<f8"), ("t_launch", "<f8"), ("t_done", "<f8")]
+ARRIVAL_DTYPE = [("t", "<f8"), ("sensor", "<i4"), ("pad_", "<i4"), ("host_range", "<u8"),
+                 ("host_labels", "<u8")]
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -104,6 +127,25 @@ def lib() -> ctypes.CDLL:
     L.flic_ctx_pass_times.restype = i32
     L.flic_last_error.argtypes = []
     L.flic_last_error.restype = ctypes.c_char_p
+    L.flic_server_create.argtypes = [vp, ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
+    L.flic_server_create.restype = i32
+    L.flic_server_add_sensor.argtypes = [vp, i32, i32, ctypes.POINTER(_Tables), f32, i32, ctypes.POINTER(i32)]
+    L.flic_server_add_sensor.restype = i32
+    L.flic_server_submit.argtypes = [vp, ctypes.c_double, ctypes.c_double, i32, vp, vp, ctypes.c_int64]
+    L.flic_server_submit.restype = i32
+    L.flic_server_progress.argtypes = [vp, ctypes.c_double, ctypes.POINTER(i32)]
+    L.flic_server_progress.restype = i32
+    L.flic_server_replay.argtypes = [vp, vp, i32]
+    L.flic_server_replay.restype = i32
+    L.flic_server_now.argtypes = [vp]
+    L.flic_server_now.restype = ctypes.c_double
+    L.flic_server_records.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.flic_server_records.restype = i32
+    L.flic_server_clear.argtypes = [vp]
+    L.flic_server_clear.restype = i32
+    L.flic_server_destroy.argtypes = [vp]
+    L.flic_server_destroy.restype = None
     _lib = L
     return L
 
@@ -490,3 +532,75 @@ def to_device(scan, device="cuda", min_points: int = 0, map_connections: int = 0
                    map_connections=map_connections)
     d.validate()          # allocates the labels tensor
     return d
+
+
+class Server:
+    """The library's serving runtime (flic_server_*): sensors, slots, FIFO
+    admission and continuous batching in native code.  ctx None: simulated
+    device (each launch takes sim_launch_s; no buffers are touched)."""
+
+    def __init__(self, ctx: Optional["Context"], n_streams: int = 3, max_batch: int = 64,
+                 slots_per_sensor: int = 3, max_queue: int = 64, hbm_budget: int = 0,
+                 sim_launch_s: float = 0.0):
+        self.ctx = ctx
+        cfg = _ServerConfig(n_streams, max_batch, slots_per_sensor, max_queue, hbm_budget, sim_launch_s)
+        h = ctypes.c_void_p()
+        _check(lib().flic_server_create(ctx.handle if ctx is not None else None, ctypes.byref(cfg),
+                                        ctypes.byref(h)))
+        self.handle = h.value
+
+    def add_sensor(self, H: int, W: int, cos_v, cos_h, threshold: float, skip_depth: int) -> int:
+        """cos_v [N][H], cos_h [N][W]: host float32 arrays (copied)."""
+        import numpy as np
+        cv = np.ascontiguousarray(cos_v, dtype=np.float32)
+        chh = np.ascontiguousarray(cos_h, dtype=np.float32)
+        sid = ctypes.c_int32()
+        t = _Tables(cv.ctypes.data, chh.ctypes.data)
+        _check(lib().flic_server_add_sensor(self.handle, H, W, ctypes.byref(t), float(threshold),
+                                            int(skip_depth), ctypes.byref(sid)))
+        return sid.value
+
+    def now(self) -> float:
+        return lib().flic_server_now(self.handle)
+
+    def submit(self, now: float, t_arrival: float, sensor: int, host_range: int = 0, host_labels: int = 0,
+               tag: int = 0) -> None:
+        _check(lib().flic_server_submit(self.handle, now, t_arrival, sensor, host_range or None,
+                                        host_labels or None, tag))
+
+    def progress(self, now: float) -> int:
+        n = ctypes.c_int32()
+        _check(lib().flic_server_progress(self.handle, now, ctypes.byref(n)))
+        return n.value
+
+    def replay(self, arrivals) -> None:
+        """arrivals: numpy array of ARRIVAL_DTYPE, times non-decreasing."""
+        import numpy as np
+        a = np.ascontiguousarray(arrivals, dtype=ARRIVAL_DTYPE)
+        assert ctypes.sizeof(_Arrival) == a.dtype.itemsize
+        _check(lib().flic_server_replay(self.handle, a.ctypes.data if len(a) else None, len(a)))
+
+    def records(self):
+        """(records as a numpy array of RECORD_DTYPE, dropped, launches)."""
+        import numpy as np
+        n, dropped, launches = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().flic_server_records(self.handle, None, 0, ctypes.byref(n), None, None))
+        out = np.zeros(n.value, dtype=RECORD_DTYPE)
+        assert ctypes.sizeof(_FrameRecord) == out.dtype.itemsize
+        _check(lib().flic_server_records(self.handle, out.ctypes.data if n.value else None, n.value,
+                                         ctypes.byref(n), ctypes.byref(dropped), ctypes.byref(launches)))
+        return out, dropped.value, launches.value
+
+    def clear(self) -> None:
+        _check(lib().flic_server_clear(self.handle))
+
+    def close(self) -> None:
+        if self.handle:
+            lib().flic_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

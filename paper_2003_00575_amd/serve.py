@@ -13,11 +13,16 @@ host memory) and an event.  Work
 from different streams overlaps on the device.  Latency is measured from a
 frame's arrival to its labels being on the host.
 
-The scheduling core is independent of the device (a backend object does the
-copies and launches), so its admission, FIFO and statistics logic is tested on
-the CPU with a fake backend and a fake clock.
+The loop exists twice.  The library's native serving runtime (flic_server_*,
+in C++: serve_native_once, the default) runs admission, FIFO, slots and
+continuous batching without the interpreter in the way; ServingCore below is
+the same policy in Python, with a backend object doing the copies and
+launches.  Its admission, FIFO and statistics logic is tested on the CPU with
+a fake backend and a fake clock, and the native runtime is tested against it
+event by event (its simulated device completes a launch a fixed time after it
+was made).
 
-    python -m paper_2003_00575_amd.serve --seconds 60 --sensors 32
+    python -m paper_2003_00575_amd.serve --seconds 60 --sensors 32 [--loop python]
 """
 from __future__ import annotations
 
@@ -203,7 +208,7 @@ class ServingCore:
                 self.free_slots[rec.sensor].append(slot)
                 n += 1
             self.inflight[i] = None
-            for s in {rec.sensor for rec, _ in fl[1]}:
+            for s in dict.fromkeys(rec.sensor for rec, _ in fl[1]):   # first-appearance order
                 self._admit(s)
         return n
 
@@ -249,23 +254,32 @@ class ServingCore:
                     sleep(min(wait, 1e-3))
 
     def stats(self, warmup_s: float = 0.0, t0: Optional[float] = None) -> dict:
-        done = [r for r in self.records if math.isfinite(r.t_done)]
-        if t0 is None:
-            t0 = min((r.t_arrival for r in self.records), default=0.0)
-        kept = [r for r in done if r.t_arrival - t0 >= warmup_s]
-        lat = [r.latency * 1e3 for r in kept]
-        # launch -> labels on the host: the device part of a frame's latency
-        # (copies, kernels, completion seen by the loop), without the queueing
-        dev = [(r.t_done - r.t_launch) * 1e3 for r in kept]
-        span = (max(r.t_done for r in kept) - min(r.t_arrival for r in kept)) if kept else math.nan
-        px = sum(self.specs[r.sensor].H * self.specs[r.sensor].W for r in kept)
-        return {"frames": len(kept), "dropped": self.dropped, "batches": self.batches,
-                "p50_ms": order_stat(lat, 0.50), "p99_ms": order_stat(lat, 0.99),
-                "launch_p50_ms": order_stat(dev, 0.50), "launch_p99_ms": order_stat(dev, 0.99),
-                "max_ms": max(lat) if lat else math.nan,
-                "scans_per_s": len(kept) / span if kept and span > 0 else math.nan,
-                "gpix_per_s": px / span / 1e9 if kept and span > 0 else math.nan,
-                "mean_batch": (len(done) / self.batches) if self.batches else 0.0}
+        return frame_stats([(r.sensor, r.t_arrival, r.t_launch, r.t_done) for r in self.records],
+                           self.specs, self.dropped, self.batches, warmup_s, t0)
+
+
+def frame_stats(frames, specs: Dict[int, "SensorSpec"], dropped: int, batches: int,
+                warmup_s: float = 0.0, t0: Optional[float] = None) -> dict:
+    """Throughput and latency of served frames: frames are (sensor,
+    t_arrival, t_launch, t_done) in seconds (t_done infinite when dropped);
+    frames that arrived in the first warmup_s seconds after t0 are left out."""
+    done = [f for f in frames if math.isfinite(f[3])]
+    if t0 is None:
+        t0 = min((f[1] for f in frames), default=0.0)
+    kept = [f for f in done if f[1] - t0 >= warmup_s]
+    lat = [(f[3] - f[1]) * 1e3 for f in kept]
+    # launch -> labels on the host: the device part of a frame's latency
+    # (copies, kernels, completion seen by the loop), without the queueing
+    dev = [(f[3] - f[2]) * 1e3 for f in kept]
+    span = (max(f[3] for f in kept) - min(f[1] for f in kept)) if kept else math.nan
+    px = sum(specs[f[0]].H * specs[f[0]].W for f in kept)
+    return {"frames": len(kept), "dropped": dropped, "batches": batches,
+            "p50_ms": order_stat(lat, 0.50), "p99_ms": order_stat(lat, 0.99),
+            "launch_p50_ms": order_stat(dev, 0.50), "launch_p99_ms": order_stat(dev, 0.99),
+            "max_ms": max(lat) if lat else math.nan,
+            "scans_per_s": len(kept) / span if kept and span > 0 else math.nan,
+            "gpix_per_s": px / span / 1e9 if kept and span > 0 else math.nan,
+            "mean_batch": (len(done) / batches) if batches else 0.0}
 
 
 # ---------------------------------------------------------------------------
@@ -458,6 +472,69 @@ def serve_once(specs, frames, tables, rates, seconds: float, speedup: float, bat
     return st, be, core
 
 
+def serve_native_once(specs, frames, tables, rates, seconds: float, speedup: float, batched: bool,
+                      n_streams: int, budget: int, seed: int = 1, warmup_s: float = 1.0,
+                      max_batch: int = 64, slots_per_sensor: int = 3, max_queue: int = 64,
+                      keep_labels: bool = False, schedule=None):
+    """The same workload served by the library's native runtime
+    (flic_server_*): admission, FIFO, slots and continuous batching run in
+    C++ inside flic_server_replay, which replays the arrival schedule in real
+    time.  With keep_labels every frame gets its own pinned label buffer and
+    the labels are returned by (sensor, frame)."""
+    import torch
+    from . import flic
+    from . import autotune
+    ctx = flic.Context(0, hbm_budget_bytes=budget)
+    autotune.apply_default(ctx)
+    srv = flic.Server(ctx, n_streams=n_streams, max_batch=max_batch if batched else 1,
+                      slots_per_sensor=slots_per_sensor, max_queue=max_queue, hbm_budget=budget)
+    spec_of = {}
+    for sp in specs:
+        cv, ch = tables[sp.sensor]
+        sid = srv.add_sensor(sp.H, sp.W, cv, ch, sp.threshold, sp.skip_depth)
+        assert sid == sp.sensor, "sensors are registered in id order"
+        spec_of[sp.sensor] = sp
+    # receive buffers (frames arrive in pinned host memory) and label buffers
+    rx = {s: [torch.from_numpy(np.ascontiguousarray(f)).pin_memory() for f in pool]
+          for s, pool in frames.items()}
+    ring = slots_per_sensor + 1
+    out = {sp.sensor: [torch.empty((sp.H, sp.W), dtype=torch.int32, pin_memory=True) for _ in range(ring)]
+           for sp in specs}
+
+    def arrivals(sched, own_buffers):
+        a = np.zeros(len(sched), dtype=flic.ARRIVAL_DTYPE)
+        kept = {}
+        for k, (t, s, f) in enumerate(sched):
+            a[k]["t"], a[k]["sensor"] = t, s
+            a[k]["host_range"] = rx[s][f % len(rx[s])].data_ptr()
+            if own_buffers:
+                buf = torch.empty((spec_of[s].H, spec_of[s].W), dtype=torch.int32, pin_memory=True)
+                kept[(s, f)] = buf
+            else:
+                buf = out[s][f % ring]
+            a[k]["host_labels"] = buf.data_ptr()
+        return a, kept
+
+    warm, _ = arrivals([(0.0, sp.sensor, 0) for sp in specs], False)
+    srv.replay(warm)                   # warm the launch paths before the clock starts
+    torch.cuda.synchronize()
+    srv.clear()
+    sched = schedule if schedule is not None else poisson_schedule(rates, seconds, seed, speedup)
+    arr, kept = arrivals(sched, keep_labels)
+    t0 = srv.now()
+    srv.replay(arr)
+    torch.cuda.synchronize()
+    rec, dropped, launches = srv.records()
+    st = frame_stats(list(zip(rec["sensor"].tolist(), rec["t_arrival"].tolist(), rec["t_launch"].tolist(),
+                              rec["t_done"].tolist())), spec_of, dropped, launches, warmup_s, t0)
+    used = ctx.bytes_in_use()
+    st.update({"mode": "batched" if batched else "per-scan", "loop": "native", "speedup": speedup,
+               "streams": n_streams, "offered_scans_per_s": sum(rates) * speedup, "ctx_bytes": used})
+    labels = {key: buf.numpy().copy() for key, buf in kept.items()} if keep_labels else None
+    srv.close()
+    return st, labels
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--sensors", type=int, default=32)
@@ -468,13 +545,20 @@ def main() -> int:
     ap.add_argument("--streams", type=int, default=3)
     ap.add_argument("--budget-gb", type=float, default=4.0)
     ap.add_argument("--p99-ms", type=float, default=10.0)
+    ap.add_argument("--loop", choices=("native", "python"), default="native",
+                    help="the library's native serving runtime, or this module's Python loop")
     args = ap.parse_args()
     specs, frames, tables, rates = make_fleet(args.sensors, args.pool)
     out = []
     for m in [float(x) for x in args.speedups.split(",")]:
         for batched in (True, False):
-            st, _, _ = serve_once(specs, frames, tables, rates, args.seconds, m, batched,
-                                  args.streams, int(args.budget_gb * 2**30), warmup_s=args.warmup)
+            if args.loop == "native":
+                st, _ = serve_native_once(specs, frames, tables, rates, args.seconds, m, batched,
+                                          args.streams, int(args.budget_gb * 2**30), warmup_s=args.warmup)
+            else:
+                st, _, _ = serve_once(specs, frames, tables, rates, args.seconds, m, batched,
+                                      args.streams, int(args.budget_gb * 2**30), warmup_s=args.warmup)
+                st["loop"] = "python"
             out.append(st)
             print(json.dumps(st), flush=True)
     for mode in ("batched", "per-scan"):

@@ -55,6 +55,54 @@ def test_served_frames_equal_alone(flic, batched):
         assert np.array_equal(d.labels.cpu().numpy(), want)
 
 
+@pytest.mark.parametrize("batched", [True, False])
+def test_native_served_frames_equal_alone(flic, batched):
+    """The library's native serving runtime: every frame's labels (each frame
+    with its own pinned label buffer) equal the oracle's for that frame alone."""
+    from paper_2003_00575_amd import serve
+    specs, frames, tables, rates = serve.make_fleet(10, pool=3, seed=5)
+    st, labels = serve.serve_native_once(specs, frames, tables, rates, seconds=0.4, speedup=4.0,
+                                         batched=batched, n_streams=3, budget=4 << 30, warmup_s=0.0,
+                                         keep_labels=True)
+    assert st["frames"] > 20 and st["dropped"] == 0 and st["loop"] == "native"
+    if not batched:
+        assert st["mean_batch"] == 1.0
+    assert len(labels) == st["frames"]
+    for (sensor, frame), got in sorted(labels.items()):
+        sp = specs[sensor]
+        pool = frames[sensor]
+        cv, ch = tables[sensor]
+        want = oracle.cluster(pool[frame % len(pool)], cv, ch, sp.threshold, sp.skip_depth)
+        assert np.array_equal(got, want), (sensor, frame)
+
+
+def test_native_budget_admission_on_device(flic):
+    """The native runtime admits a sensor only while its tables and slots plus
+    the context's launch ring fit the budget."""
+    from paper_2003_00575_amd import serve
+    specs, frames, tables, rates = serve.make_fleet(6, pool=1, seed=2)
+    slots = 2
+    resident = [sp.skip_depth * (sp.H + sp.W) * 4 + slots * sp.H * sp.W * 8 for sp in specs]
+    probe_ctx = flic.Context(0)
+    probe = flic.Server(probe_ctx, n_streams=2, max_batch=4, slots_per_sensor=slots)
+    for sp in specs[:2]:
+        probe.add_sensor(sp.H, sp.W, *tables[sp.sensor], sp.threshold, sp.skip_depth)
+    ring = probe_ctx.bytes_in_use()
+    probe.close()
+    assert ring > 0
+    ctx = flic.Context(0)
+    srv = flic.Server(ctx, n_streams=2, max_batch=4, slots_per_sensor=slots,
+                      hbm_budget=resident[0] + resident[1] + ring)
+    for sp in specs[:2]:
+        srv.add_sensor(sp.H, sp.W, *tables[sp.sensor], sp.threshold, sp.skip_depth)
+    assert ctx.bytes_in_use() == ring
+    big = max(specs[2:], key=lambda s: s.H * s.W)
+    with pytest.raises(flic.FlicError) as e:
+        srv.add_sensor(big.H, big.W, *tables[big.sensor], big.threshold, big.skip_depth)
+    assert e.value.status == flic.FLIC_ENOMEM
+    srv.close()
+
+
 def test_budget_admission_on_device(flic):
     from paper_2003_00575_amd import serve
     specs, frames, tables, rates = serve.make_fleet(6, pool=1, seed=2)
