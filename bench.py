@@ -294,7 +294,7 @@ def ground_extraction(flic, synth, torch, host, ranges, dev, stream, reps=30):
                          "rocprof_mean_us": rec.get("mean_us") if rec else None}}
 
 
-def serving_excerpt(seconds, speedups=(16.0, 32.0, 48.0, 64.0, 80.0, 96.0), sensors=32, p99_limit_ms=10.0):
+def serving_excerpt(seconds, speedups=(16.0, 32.0, 48.0, 64.0, 72.0, 80.0), sensors=32, p99_limit_ms=10.0):
     """Continuous batching vs per-scan launches for 32 simulated sensors,
     swept over time-compression factors up to per-scan saturation; reports
     each mode's highest throughput whose p99 stays within the limit."""
@@ -337,7 +337,7 @@ def main() -> int:
     ap.add_argument("--no-uneven", action="store_true", help="skip the 256-scan mixed batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving excerpt")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
-    ap.add_argument("--serve-speedups", default="16,32,48,64,80,96",
+    ap.add_argument("--serve-speedups", default="16,32,48,64,72,80",
                     help="time-compression factors of the serving sweep")
     ap.add_argument("--no-stress", action="store_true", help="skip the union-find stress set")
     ap.add_argument("--plan-parts", type=int, default=1,

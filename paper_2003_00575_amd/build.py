@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflic.so")
 SOURCES = [os.path.join(CSRC, "flic_kernels.hip"), os.path.join(CSRC, "flic_api.cpp"),
            os.path.join(CSRC, "flic_ground.hip"), os.path.join(CSRC, "flic_noalloc.hip"),
-           os.path.join(CSRC, "flic_serve.cpp")]
+           os.path.join(CSRC, "flic_serve.cpp"), os.path.join(CSRC, "flic_stage.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: the edge test must be a chain of separately rounded

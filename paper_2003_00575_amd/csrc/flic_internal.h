@@ -159,6 +159,21 @@ constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
 constexpr int kMaxDevices = 64;
 hipError_t noalloc_scratch(int device, void** out);
 
+// Batched staging copies of the serving runtime (k_stage): item i moves
+// `bytes` (a multiple of 4) from src to dst, both 16-byte aligned; one
+// workgroup per kStageChunk bytes of an item.
+struct StageItem {
+    const void* src;
+    void* dst;
+    uint64_t bytes;
+};
+constexpr int kStageMax = 64;
+constexpr uint64_t kStageChunk = uint64_t(64) << 10;
+struct StageList {
+    StageItem item[kStageMax];
+};
+hipError_t launch_stage(const StageList& list, int n, uint64_t max_bytes, hipStream_t stream);
+
 }  // namespace flic
 
 // Shared by the host files: the message flic_last_error returns on this

@@ -2,9 +2,11 @@
 // they arrive (the real-time, frame-by-frame use of Section IV.A), frames that
 // are ready together sharing one batched launch.  Admission against an HBM
 // budget, FIFO per sensor with drop-oldest backpressure, per-sensor device
-// frame slots, continuous batching over several launch streams.  The launch
-// itself is flic_cluster_batched_host (copies in, the three passes, labels
-// out) on the context the caller owns.
+// frame slots, continuous batching over several launch streams.  A launch is
+// the frames' copies in, flic_cluster_batched on the context the caller owns,
+// and the labels' copies out: one DMA copy per frame and direction
+// (flic_cluster_batched_host), or one staging kernel per direction for the
+// whole batch (k_stage, flic_stage.hip).
 #include "../../include/flic.h"
 
 #include <hip/hip_runtime.h>
@@ -17,6 +19,7 @@
 #include <deque>
 #include <limits>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "flic_internal.h"
@@ -57,6 +60,7 @@ struct Sensor {
 
 struct Frame {
     int32_t sensor = 0, slot = -1, batch = -1;
+    bool staged = false;                   // its host buffers go through the copy kernels
     int64_t tag = 0;
     const float* h_in = nullptr;
     int32_t* h_out = nullptr;
@@ -88,11 +92,33 @@ struct flic_server {
     std::vector<flic_scan> scans;
     std::vector<const float*> h_in;
     std::vector<int32_t*> h_out;
+    // host ranges the runtime reported device-accessible at their own address
+    std::unordered_map<const void*, size_t> visible;
 };
 
 namespace {
 
 bool device_mode(const flic_server* s) { return s->ctx != nullptr; }
+
+// Whether the device can read and write [p, p + bytes) at the same addresses
+// (pinned host memory mapped into the device's address space), both ends
+// asked of the HIP runtime; remembered per buffer.
+bool device_visible(flic_server* s, const void* p, size_t bytes) {
+    if (!p || bytes == 0 || (reinterpret_cast<uintptr_t>(p) & 15)) return false;
+    const auto it = s->visible.find(p);
+    if (it != s->visible.end() && it->second >= bytes) return true;
+    const char* ends[2] = {static_cast<const char*>(p), static_cast<const char*>(p) + bytes - 1};
+    for (const char* q : ends) {
+        hipPointerAttribute_t a{};
+        if (hipPointerGetAttributes(&a, q) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (a.type != hipMemoryTypeHost || a.devicePointer != q) return false;
+    }
+    s->visible[p] = bytes;
+    return true;
+}
 
 void free_sensor(Sensor& sn) {
     for (float* p : sn.range) (void)hipFree(p);
@@ -177,9 +203,43 @@ flic_status launch(flic_server* s, int i, double now) {
         s->h_in[k] = fr.h_in;
         s->h_out[k] = fr.h_out;
     }
-    const flic_status st =
-        flic_cluster_batched_host(s->ctx, s->scans.data(), n, s->h_in.data(), s->h_out.data(), s->streams[i]);
-    if (st != FLIC_OK) return st;
+    if (!s->cfg.stage_kernels) {
+        const flic_status st = flic_cluster_batched_host(s->ctx, s->scans.data(), n, s->h_in.data(),
+                                                         s->h_out.data(), s->streams[i]);
+        if (st != FLIC_OK) return st;
+    } else {
+        // frames in: one copy kernel per kStageMax staged frames, a DMA copy
+        // for any other; then the batched launch; then the labels out
+        for (int dir = 0; dir < 2; ++dir) {
+            if (dir == 1) {
+                const flic_status st = flic_cluster_batched(s->ctx, s->scans.data(), n, s->streams[i]);
+                if (st != FLIC_OK) return st;
+            }
+            flic::StageList list{};
+            int m = 0;
+            uint64_t most = 0;
+            for (int k = 0; k < n; ++k) {
+                const Frame& fr = s->frames[fl.frames[k]];
+                const flic_scan& sc = s->scans[k];
+                const size_t bytes = (size_t)sc.H * sc.W * 4;
+                const void* src = dir == 0 ? static_cast<const void*>(fr.h_in) : sc.labels_out;
+                void* dst = dir == 0 ? const_cast<float*>(sc.range_img) : static_cast<void*>(fr.h_out);
+                if (!fr.staged) {
+                    SRV_HIP(hipMemcpyAsync(dst, src, bytes, dir == 0 ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost,
+                                           s->streams[i]));
+                    continue;
+                }
+                list.item[m++] = flic::StageItem{src, dst, bytes};
+                most = std::max<uint64_t>(most, bytes);
+                if (m == flic::kStageMax || k == n - 1) {
+                    SRV_HIP(flic::launch_stage(list, m, most, s->streams[i]));
+                    m = 0;
+                    most = 0;
+                }
+            }
+            if (m > 0) SRV_HIP(flic::launch_stage(list, m, most, s->streams[i]));
+        }
+    }
     SRV_HIP(hipEventRecord(s->done[i], s->streams[i]));
     return FLIC_OK;
 }
@@ -317,6 +377,10 @@ flic_status flic_server_submit(flic_server* s, double now, double t_arrival, int
     fr.h_in = host_range;
     fr.h_out = host_labels;
     fr.t_arrival = t_arrival;
+    if (device_mode(s) && s->cfg.stage_kernels) {
+        const size_t bytes = (size_t)sn.H * sn.W * 4;
+        fr.staged = device_visible(s, host_range, bytes) && device_visible(s, host_labels, bytes);
+    }
     const int32_t idx = (int32_t)s->frames.size();
     s->frames.push_back(fr);
     if ((int32_t)sn.waiting.size() >= s->cfg.max_queue) {

@@ -49,7 +49,8 @@ class _GroundTables(ctypes.Structure):
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("slots_per_sensor", ctypes.c_int32), ("max_queue", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_uint64), ("sim_launch_s", ctypes.c_double)]
+                ("hbm_budget", ctypes.c_uint64), ("sim_launch_s", ctypes.c_double),
+                ("stage_kernels", ctypes.c_int32)]
 
 
 class _FrameRecord(ctypes.Structure):
@@ -541,9 +542,10 @@ class Server:
 
     def __init__(self, ctx: Optional["Context"], n_streams: int = 3, max_batch: int = 64,
                  slots_per_sensor: int = 3, max_queue: int = 64, hbm_budget: int = 0,
-                 sim_launch_s: float = 0.0):
+                 sim_launch_s: float = 0.0, stage_kernels: bool = False):
         self.ctx = ctx
-        cfg = _ServerConfig(n_streams, max_batch, slots_per_sensor, max_queue, hbm_budget, sim_launch_s)
+        cfg = _ServerConfig(n_streams, max_batch, slots_per_sensor, max_queue, hbm_budget, sim_launch_s,
+                            1 if stage_kernels else 0)
         h = ctypes.c_void_p()
         _check(lib().flic_server_create(ctx.handle if ctx is not None else None, ctypes.byref(cfg),
                                         ctypes.byref(h)))

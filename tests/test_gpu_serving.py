@@ -55,15 +55,15 @@ def test_served_frames_equal_alone(flic, batched):
         assert np.array_equal(d.labels.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("batched", [True, False])
-def test_native_served_frames_equal_alone(flic, batched):
+@pytest.mark.parametrize("batched,stage_kernels", [(True, True), (False, True), (True, False)])
+def test_native_served_frames_equal_alone(flic, batched, stage_kernels):
     """The library's native serving runtime: every frame's labels (each frame
     with its own pinned label buffer) equal the oracle's for that frame alone."""
     from paper_2003_00575_amd import serve
     specs, frames, tables, rates = serve.make_fleet(10, pool=3, seed=5)
     st, labels = serve.serve_native_once(specs, frames, tables, rates, seconds=0.4, speedup=4.0,
                                          batched=batched, n_streams=3, budget=4 << 30, warmup_s=0.0,
-                                         keep_labels=True)
+                                         keep_labels=True, stage_kernels=stage_kernels)
     assert st["frames"] > 20 and st["dropped"] == 0 and st["loop"] == "native"
     if not batched:
         assert st["mean_batch"] == 1.0
