@@ -64,23 +64,30 @@ def test_oracle_under_asan_and_ubsan(tmp_path):
 
 
 def test_host_api_under_asan_and_ubsan(tmp_path):
-    """flic_api.cpp's argument checks (the C-ABI validation tests) with the
-    host half of the translation unit sanitized; the device code and the
-    kernel objects are the regular build's."""
+    """The host files (flic_api.cpp: argument checks; flic_serve.cpp: the
+    serving runtime's scheduler, run on its simulated device) with their host
+    halves sanitized, exercised by the C-ABI validation tests and the native
+    serving tests; the device code and the kernel objects are the regular
+    build's."""
     from paper_2003_00575_amd import build
+    host_files = ("flic_api", "flic_serve")
     objs = [os.path.join(build.OBJ_DIR, f) for f in sorted(os.listdir(build.OBJ_DIR))
-            if f.endswith(".o") and f != "flic_api.o"] if os.path.isdir(build.OBJ_DIR) else []
+            if f.endswith(".o") and f[:-2] not in host_files] if os.path.isdir(build.OBJ_DIR) else []
     if not any("flic_kernels" in o for o in objs):
         pytest.skip("kernel objects not built")
-    api_obj = str(tmp_path / "flic_api_san.o")
     host_san = [a for f in SAN[:2] for a in ("-Xarch_host", f)] + ["-fno-omit-frame-pointer", "-g"]
-    subprocess.check_call([build.HIPCC, *build.FLAGS, *host_san, "-c", "-o", api_obj,
-                           os.path.join(build.CSRC, "flic_api.cpp")])
+    san_objs = []
+    for name in host_files:
+        obj = str(tmp_path / f"{name}_san.o")
+        subprocess.check_call([build.HIPCC, *build.FLAGS, *host_san, "-c", "-o", obj,
+                               os.path.join(build.CSRC, name + ".cpp")])
+        san_objs.append(obj)
     lib = str(tmp_path / "libflic_san.so")
     subprocess.check_call([build.HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *host_san,
-                           "-o", lib, api_obj, *objs])
+                           "-o", lib, *san_objs, *objs])
     env = _sanitized_env({"FLIC_LIB": lib}, _clang_runtime())
     out = _run(["-c", "from paper_2003_00575_amd import flic; flic.lib(); print(flic.LIB_PATH)"], env)
     assert lib in out
-    out = _run(["-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "tests/test_abi.py"], env)
+    out = _run(["-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "tests/test_abi.py",
+                "tests/test_serve_native.py"], env)
     assert " passed" in out
