@@ -362,8 +362,9 @@ flic_status flic_server_create(flic_ctx* ctx, const flic_server_config* cfg, fli
  * (metres); host_tables holds host pointers to the angle tables in the
  * layout of flic_alpha_tables (copied to the device).  The sensor's id is
  * written to *sensor_out (0, 1, ... in registration order).  FLIC_EINVAL
- * for arguments flic_cluster would reject; FLIC_ENOMEM (nothing kept) when
- * the budget or a device allocation does not allow it.                    */
+ * for arguments flic_cluster would reject; FLIC_ENOMEM when the budget or a
+ * device allocation does not allow it: nothing of the sensor is kept, but
+ * the context's launch ring stays grown if a larger shape made it grow.   */
 flic_status flic_server_add_sensor(flic_server* srv, int32_t H, int32_t W, const flic_alpha_tables* host_tables,
                                    float threshold, int32_t skip_depth, int32_t* sensor_out);
 
