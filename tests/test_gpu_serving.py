@@ -145,3 +145,52 @@ def test_autotune_rules_keep_labels(flic, tmp_path):
         ctx.cluster_async(d)
         torch.cuda.synchronize()
         assert np.array_equal(d.labels.cpu().numpy(), want), tw
+
+
+def test_native_staging_tail_and_pageable_fallback(flic):
+    """The native runtime with staging kernels on frames whose size is not a
+    multiple of 16 bytes (31 x 1001: the kernel's 4-byte tail) in pinned
+    buffers, and on frames in pageable numpy buffers (not device-accessible:
+    each falls back to DMA copies); every frame's labels equal the oracle's."""
+    shapes = [(31, 1001, 3, 0.6), (16, 1024, 2, 0.4)]
+    scans = {s: [synth.synth_scan(H, W, 10.0, -20.0, 12, "iid10", 40 + 10 * s + f, T, N) for f in range(3)]
+             for s, (H, W, N, T) in enumerate(shapes)}
+    ctx = flic.Context(0)
+    srv = flic.Server(ctx, n_streams=2, max_batch=8, slots_per_sensor=2, stage_kernels=True)
+    for s, (H, W, N, T) in enumerate(shapes):
+        sc = scans[s][0]
+        assert srv.add_sensor(H, W, sc.cos_v, sc.cos_h, T, N) == s
+    keep = []
+    expect = {}
+    tag = 0
+    for rep in range(2):
+        for s, (H, W, N, T) in enumerate(shapes):
+            for f, sc in enumerate(scans[s]):
+                if rep == 0:                    # pinned: staged by the kernel
+                    src = torch.from_numpy(sc.range_img.copy()).pin_memory()
+                    dst = torch.full((H, W), -7, dtype=torch.int32).pin_memory()
+                    ptrs = (src.data_ptr(), dst.data_ptr())
+                    out = dst
+                else:                           # pageable: DMA copies
+                    src = np.ascontiguousarray(sc.range_img)
+                    dst = np.full((H, W), -7, dtype=np.int32)
+                    ptrs = (src.ctypes.data, dst.ctypes.data)
+                    out = dst
+                keep.append((src, dst))
+                now = srv.now()
+                srv.submit(now, now, s, ptrs[0], ptrs[1], tag)
+                expect[tag] = (out, oracle.cluster(sc.range_img, sc.cos_v, sc.cos_h, T, N))
+                tag += 1
+                srv.progress(srv.now())
+    for _ in range(100000):
+        srv.progress(srv.now())
+        rec, dropped, launches = srv.records()
+        if np.all(np.isfinite(rec["t_done"])):
+            break
+    torch.cuda.synchronize()
+    rec, dropped, launches = srv.records()
+    assert dropped == 0 and len(rec) == tag and np.all(np.isfinite(rec["t_done"]))
+    for t, (out, want) in expect.items():
+        got = out.numpy() if hasattr(out, "numpy") else out
+        assert np.array_equal(got, want), t
+    srv.close()
