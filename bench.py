@@ -532,6 +532,22 @@ def main() -> int:
         b.synchronize()
         lat_host.append((time.perf_counter() - t) * 1e3)
         lat_dev.append(a.elapsed_time(b))
+    # the same scan as a one-scan plan (a hipGraph of its passes), as a sensor
+    # with a fixed shape would run it frame after frame
+    p1 = ctx.plan([d1])
+    for _ in range(20):
+        p1.relaunch(stream)
+    torch.cuda.synchronize()
+    plan_host, plan_dev = [], []
+    for _ in range(args.latency_reps):
+        t = time.perf_counter()
+        a.record(stream)
+        p1.relaunch(stream)
+        b.record(stream)
+        b.synchronize()
+        plan_host.append((time.perf_counter() - t) * 1e3)
+        plan_dev.append(a.elapsed_time(b))
+    p1.close()
 
     if args.copy_calibration:
         src = torch.empty(32 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
@@ -636,7 +652,11 @@ def main() -> int:
                        "host_p50": round(percentile(lat_host, 0.5), 4),
                        "host_p99": round(percentile(lat_host, 0.99), 4),
                        "device_p50": round(percentile(lat_dev, 0.5), 4),
-                       "device_p99": round(percentile(lat_dev, 0.99), 4)},
+                       "device_p99": round(percentile(lat_dev, 0.99), 4),
+                       "plan": {"host_p50": round(percentile(plan_host, 0.5), 4),
+                                "host_p99": round(percentile(plan_host, 0.99), 4),
+                                "device_p50": round(percentile(plan_dev, 0.5), 4),
+                                "device_p99": round(percentile(plan_dev, 0.99), 4)}},
         "uneven_batch": uneven,
         "ground_extraction": ground,
         "serving": serving,
