@@ -306,11 +306,12 @@ flic_status flic_ground_remove(flic_ctx* ctx, const float* range_in, int32_t n_s
  * whole arrival schedule in real time.  A server is used by one thread at a
  * time.  Host buffers should be pinned (hipHostMalloc) for the copies to be
  * asynchronous; each must stay valid until its frame is done.  With
- * stage_kernels, a batch's frames move between host and device buffers in
+ * stage_kernels 1, a batch's frames move between host and device buffers in
  * one kernel launch per direction that reads (writes) the host buffers
- * directly; a frame whose buffers the HIP runtime does not report as
- * device-accessible at the same address (or that are not 16-byte aligned)
- * is copied with hipMemcpyAsync instead.
+ * directly; with 2, the clustering passes themselves read the ranges from
+ * and write the labels to the host buffers.  A frame whose buffers the HIP
+ * runtime does not report as device-accessible at the same address (or that
+ * are not 16-byte aligned) is copied with hipMemcpyAsync instead.
  *
  * With ctx == NULL the server simulates the device: nothing is allocated or
  * launched, and a launch is done sim_launch_s seconds after it was made
@@ -324,9 +325,10 @@ typedef struct {
     int32_t max_queue;        /* waiting frames per sensor before drops, >= 1    */
     uint64_t hbm_budget;      /* bytes: tables + slots + launch ring; 0 = no cap */
     double sim_launch_s;      /* simulated launch duration (ctx == NULL), >= 0   */
-    int32_t stage_kernels;    /* 1: move a batch's frames with one copy kernel   */
-                              /* each way (see below); 0: one hipMemcpyAsync per */
-                              /* frame and direction                             */
+    int32_t stage_kernels;    /* 0: one hipMemcpyAsync per frame and direction;  */
+                              /* 1: one copy kernel per batch and direction;     */
+                              /* 2: no copies, the passes read and write the     */
+                              /* host buffers (see below)                        */
 } flic_server_config;
 
 /* One frame's history.  batch is the launch's sequence number (-1 when the

@@ -200,6 +200,10 @@ flic_status launch(flic_server* s, int i, double now) {
         sc.threshold = sn.T;
         sc.skip_depth = sn.N;
         sc.labels_out = sn.labels[fr.slot];
+        if (s->cfg.stage_kernels == 2 && fr.staged) {     // the passes read and write the host buffers
+            sc.range_img = fr.h_in;
+            sc.labels_out = fr.h_out;
+        }
         s->h_in[k] = fr.h_in;
         s->h_out[k] = fr.h_out;
     }
@@ -222,6 +226,7 @@ flic_status launch(flic_server* s, int i, double now) {
                 const Frame& fr = s->frames[fl.frames[k]];
                 const flic_scan& sc = s->scans[k];
                 const size_t bytes = (size_t)sc.H * sc.W * 4;
+                if (fr.staged && s->cfg.stage_kernels == 2) continue;   // no copy at all
                 const void* src = dir == 0 ? static_cast<const void*>(fr.h_in) : sc.labels_out;
                 void* dst = dir == 0 ? const_cast<float*>(sc.range_img) : static_cast<void*>(fr.h_out);
                 if (!fr.staged) {
@@ -272,6 +277,8 @@ flic_status flic_server_create(flic_ctx* ctx, const flic_server_config* cfg, fli
     if (c.slots_per_sensor < 1 || c.slots_per_sensor > 16)
         return sfail(FLIC_EINVAL, "slots_per_sensor %d outside 1..16", c.slots_per_sensor);
     if (c.max_queue < 1) return sfail(FLIC_EINVAL, "max_queue %d < 1", c.max_queue);
+    if (c.stage_kernels < 0 || c.stage_kernels > 2)
+        return sfail(FLIC_EINVAL, "stage_kernels %d outside 0..2", c.stage_kernels);
     if (!ctx && !(std::isfinite(c.sim_launch_s) && c.sim_launch_s >= 0.0))
         return sfail(FLIC_EINVAL, "sim_launch_s must be finite and >= 0");
     flic_server* s = new flic_server();

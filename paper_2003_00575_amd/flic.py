@@ -542,10 +542,10 @@ class Server:
 
     def __init__(self, ctx: Optional["Context"], n_streams: int = 3, max_batch: int = 64,
                  slots_per_sensor: int = 3, max_queue: int = 64, hbm_budget: int = 0,
-                 sim_launch_s: float = 0.0, stage_kernels: bool = False):
+                 sim_launch_s: float = 0.0, stage_kernels: int = 0):
         self.ctx = ctx
         cfg = _ServerConfig(n_streams, max_batch, slots_per_sensor, max_queue, hbm_budget, sim_launch_s,
-                            1 if stage_kernels else 0)
+                            int(stage_kernels))
         h = ctypes.c_void_p()
         _check(lib().flic_server_create(ctx.handle if ctx is not None else None, ctypes.byref(cfg),
                                         ctypes.byref(h)))

@@ -474,8 +474,8 @@ def serve_once(specs, frames, tables, rates, seconds: float, speedup: float, bat
 
 def serve_native_once(specs, frames, tables, rates, seconds: float, speedup: float, batched: bool,
                       n_streams: int, budget: int, seed: int = 1, warmup_s: float = 1.0,
-                      max_batch: int = 64, slots_per_sensor: int = 3, max_queue: int = 64,
-                      keep_labels: bool = False, schedule=None, stage_kernels: bool = True):
+                      max_batch: int = 64, slots_per_sensor: int = 8, max_queue: int = 64,
+                      keep_labels: bool = False, schedule=None, copies: str = "kernel"):
     """The same workload served by the library's native runtime
     (flic_server_*): admission, FIFO, slots and continuous batching run in
     C++ inside flic_server_replay, which replays the arrival schedule in real
@@ -488,7 +488,7 @@ def serve_native_once(specs, frames, tables, rates, seconds: float, speedup: flo
     autotune.apply_default(ctx)
     srv = flic.Server(ctx, n_streams=n_streams, max_batch=max_batch if batched else 1,
                       slots_per_sensor=slots_per_sensor, max_queue=max_queue, hbm_budget=budget,
-                      stage_kernels=stage_kernels)
+                      stage_kernels={"dma": 0, "kernel": 1, "direct": 2}[copies])
     spec_of = {}
     for sp in specs:
         cv, ch = tables[sp.sensor]
@@ -530,7 +530,7 @@ def serve_native_once(specs, frames, tables, rates, seconds: float, speedup: flo
                               rec["t_done"].tolist())), spec_of, dropped, launches, warmup_s, t0)
     used = ctx.bytes_in_use()
     st.update({"mode": "batched" if batched else "per-scan", "loop": "native",
-               "copies": "kernel" if stage_kernels else "dma", "speedup": speedup,
+               "copies": copies, "speedup": speedup,
                "streams": n_streams, "offered_scans_per_s": sum(rates) * speedup, "ctx_bytes": used})
     labels = {key: buf.numpy().copy() for key, buf in kept.items()} if keep_labels else None
     srv.close()
@@ -549,8 +549,10 @@ def main() -> int:
     ap.add_argument("--p99-ms", type=float, default=10.0)
     ap.add_argument("--loop", choices=("native", "python"), default="native",
                     help="the library's native serving runtime, or this module's Python loop")
-    ap.add_argument("--copies", choices=("kernel", "dma"), default="kernel",
-                    help="native loop: one staging kernel per batch and direction, or a DMA copy per frame")
+    ap.add_argument("--slots", type=int, default=8, help="device frame slots per sensor (native loop)")
+    ap.add_argument("--copies", choices=("kernel", "dma", "direct"), default="kernel",
+                    help="native loop: one staging kernel per batch and direction, a DMA copy per frame, "
+                         "or none (the passes read and write the pinned host buffers)")
     args = ap.parse_args()
     specs, frames, tables, rates = make_fleet(args.sensors, args.pool)
     out = []
@@ -559,7 +561,7 @@ def main() -> int:
             if args.loop == "native":
                 st, _ = serve_native_once(specs, frames, tables, rates, args.seconds, m, batched,
                                           args.streams, int(args.budget_gb * 2**30), warmup_s=args.warmup,
-                                          stage_kernels=args.copies == "kernel")
+                                          copies=args.copies, slots_per_sensor=args.slots)
             else:
                 st, _, _ = serve_once(specs, frames, tables, rates, args.seconds, m, batched,
                                       args.streams, int(args.budget_gb * 2**30), warmup_s=args.warmup)

@@ -55,15 +55,15 @@ def test_served_frames_equal_alone(flic, batched):
         assert np.array_equal(d.labels.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("batched,stage_kernels", [(True, True), (False, True), (True, False)])
-def test_native_served_frames_equal_alone(flic, batched, stage_kernels):
+@pytest.mark.parametrize("batched,copies", [(True, "kernel"), (False, "kernel"), (True, "dma"), (True, "direct")])
+def test_native_served_frames_equal_alone(flic, batched, copies):
     """The library's native serving runtime: every frame's labels (each frame
     with its own pinned label buffer) equal the oracle's for that frame alone."""
     from paper_2003_00575_amd import serve
     specs, frames, tables, rates = serve.make_fleet(10, pool=3, seed=5)
     st, labels = serve.serve_native_once(specs, frames, tables, rates, seconds=0.4, speedup=4.0,
                                          batched=batched, n_streams=3, budget=4 << 30, warmup_s=0.0,
-                                         keep_labels=True, stage_kernels=stage_kernels)
+                                         keep_labels=True, copies=copies)
     assert st["frames"] > 20 and st["dropped"] == 0 and st["loop"] == "native"
     if not batched:
         assert st["mean_batch"] == 1.0
@@ -147,7 +147,8 @@ def test_autotune_rules_keep_labels(flic, tmp_path):
         assert np.array_equal(d.labels.cpu().numpy(), want), tw
 
 
-def test_native_staging_tail_and_pageable_fallback(flic):
+@pytest.mark.parametrize("stage", [1, 2])
+def test_native_staging_tail_and_pageable_fallback(flic, stage):
     """The native runtime with staging kernels on frames whose size is not a
     multiple of 16 bytes (31 x 1001: the kernel's 4-byte tail) in pinned
     buffers, and on frames in pageable numpy buffers (not device-accessible:
@@ -156,7 +157,7 @@ def test_native_staging_tail_and_pageable_fallback(flic):
     scans = {s: [synth.synth_scan(H, W, 10.0, -20.0, 12, "iid10", 40 + 10 * s + f, T, N) for f in range(3)]
              for s, (H, W, N, T) in enumerate(shapes)}
     ctx = flic.Context(0)
-    srv = flic.Server(ctx, n_streams=2, max_batch=8, slots_per_sensor=2, stage_kernels=True)
+    srv = flic.Server(ctx, n_streams=2, max_batch=8, slots_per_sensor=2, stage_kernels=stage)
     for s, (H, W, N, T) in enumerate(shapes):
         sc = scans[s][0]
         assert srv.add_sensor(H, W, sc.cos_v, sc.cos_h, T, N) == s

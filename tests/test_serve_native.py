@@ -125,7 +125,8 @@ def test_budget_admission():
 
 @pytest.mark.parametrize("kw", [dict(n_streams=0), dict(n_streams=9), dict(max_batch=0), dict(max_batch=1025),
                                 dict(slots_per_sensor=0), dict(slots_per_sensor=17), dict(max_queue=0),
-                                dict(sim_launch_s=-1.0), dict(sim_launch_s=float("inf"))])
+                                dict(sim_launch_s=-1.0), dict(sim_launch_s=float("inf")),
+                                dict(stage_kernels=3), dict(stage_kernels=-1)])
 def test_config_checked(kw):
     with pytest.raises(flic.FlicError) as e:
         flic.Server(None, **kw)
