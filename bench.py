@@ -100,7 +100,7 @@ def cpu_model():
 
 
 def host_threads(cap=16):
-    """Host cores this process may use (the GPU machine grants one GPU's share)."""
+    """Host cores this process may use (its CPU affinity, at most 16)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
