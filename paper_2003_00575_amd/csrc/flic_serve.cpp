@@ -94,6 +94,7 @@ struct flic_server {
     std::vector<int32_t*> h_out;
     // host ranges the runtime reported device-accessible at their own address
     std::unordered_map<const void*, size_t> visible;
+    std::vector<char> direct;              // per frame of the launch being built: passes use its host buffers
 };
 
 namespace {
@@ -144,6 +145,30 @@ flic_scan shape_only(int32_t H, int32_t W, int32_t N, float T) {
     return s;
 }
 
+// Whether frame k's host buffers, used directly by the passes, would overlap
+// the host buffers of an earlier direct frame of the same launch (the batch's
+// output buffers must be disjoint from every other buffer of the batch);
+// such a frame goes through its device slot instead.
+bool overlaps_direct(const flic_server* s, int k, const float* in, const int32_t* out, const Sensor& sn) {
+    const size_t bytes = (size_t)sn.H * sn.W * 4;
+    const char* ia = reinterpret_cast<const char*>(in);
+    const char* oa = reinterpret_cast<const char*>(out);
+    if (ia < oa + bytes && oa < ia + bytes) return true;
+    for (int q = 0; q < k; ++q) {
+        if (!s->direct[q]) continue;
+        const flic_scan& o = s->scans[q];
+        const size_t ob = (size_t)o.H * o.W * 4;
+        const char* qi = reinterpret_cast<const char*>(o.range_img);
+        const char* qo = reinterpret_cast<const char*>(o.labels_out);
+        // this frame's labels against the other's range and labels; this
+        // frame's range against the other's labels
+        if ((oa < qi + ob && qi < oa + bytes) || (oa < qo + ob && qo < oa + bytes) ||
+            (ia < qo + ob && qo < ia + bytes))
+            return true;
+    }
+    return false;
+}
+
 // Frames of `sensor` waiting for a slot take free slots, oldest first.
 void admit(flic_server* s, int32_t sensor, double now) {
     Sensor& sn = s->sensors[sensor];
@@ -187,6 +212,7 @@ flic_status launch(flic_server* s, int i, double now) {
     s->scans.resize(n);
     s->h_in.resize(n);
     s->h_out.resize(n);
+    s->direct.assign(n, 0);
     for (int k = 0; k < n; ++k) {
         const Frame& fr = s->frames[fl.frames[k]];
         const Sensor& sn = s->sensors[fr.sensor];
@@ -200,9 +226,10 @@ flic_status launch(flic_server* s, int i, double now) {
         sc.threshold = sn.T;
         sc.skip_depth = sn.N;
         sc.labels_out = sn.labels[fr.slot];
-        if (s->cfg.stage_kernels == 2 && fr.staged) {     // the passes read and write the host buffers
-            sc.range_img = fr.h_in;
+        if (s->cfg.stage_kernels == 2 && fr.staged && !overlaps_direct(s, k, fr.h_in, fr.h_out, sn)) {
+            sc.range_img = fr.h_in;                   // the passes read and write the host buffers
             sc.labels_out = fr.h_out;
+            s->direct[k] = 1;
         }
         s->h_in[k] = fr.h_in;
         s->h_out[k] = fr.h_out;
@@ -226,7 +253,7 @@ flic_status launch(flic_server* s, int i, double now) {
                 const Frame& fr = s->frames[fl.frames[k]];
                 const flic_scan& sc = s->scans[k];
                 const size_t bytes = (size_t)sc.H * sc.W * 4;
-                if (fr.staged && s->cfg.stage_kernels == 2) continue;   // no copy at all
+                if (s->direct[k]) continue;                 // no copy at all
                 const void* src = dir == 0 ? static_cast<const void*>(fr.h_in) : sc.labels_out;
                 void* dst = dir == 0 ? const_cast<float*>(sc.range_img) : static_cast<void*>(fr.h_out);
                 if (!fr.staged) {

@@ -195,3 +195,31 @@ def test_native_staging_tail_and_pageable_fallback(flic, stage):
         got = out.numpy() if hasattr(out, "numpy") else out
         assert np.array_equal(got, want), t
     srv.close()
+
+
+def test_native_direct_frames_sharing_buffers(flic):
+    """Direct mode (the passes read and write the host buffers) with frames of
+    one batch that share their host buffers: a batch's output buffers must not
+    overlap any other buffer of it, so the runtime sends such frames through
+    their device slots; every frame is served and the labels are right."""
+    sc = synth.synth_scan(32, 1800, 10.0, -20.0, 12, "iid10", 77, 0.5, 3)
+    ctx = flic.Context(0)
+    srv = flic.Server(ctx, n_streams=1, max_batch=8, slots_per_sensor=4, stage_kernels=2)
+    sid = srv.add_sensor(32, 1800, sc.cos_v, sc.cos_h, 0.5, 3)
+    src = torch.from_numpy(sc.range_img.copy()).pin_memory()
+    dst = torch.full((32, 1800), -7, dtype=torch.int32).pin_memory()
+    for k in range(4):
+        now = srv.now()
+        srv.submit(now, now, sid, src.data_ptr(), dst.data_ptr(), k)
+    for _ in range(100000):
+        srv.progress(srv.now())
+        rec, dropped, launches = srv.records()
+        if np.all(np.isfinite(rec["t_done"])):
+            break
+    torch.cuda.synchronize()
+    rec, dropped, launches = srv.records()
+    assert len(rec) == 4 and dropped == 0 and np.all(np.isfinite(rec["t_done"]))
+    assert launches == 1                                   # one batch of all four
+    want = oracle.cluster(sc.range_img, sc.cos_v, sc.cos_h, 0.5, 3)
+    assert np.array_equal(dst.numpy(), want)
+    srv.close()
