@@ -19,7 +19,6 @@
 #include <deque>
 #include <limits>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "flic_internal.h"
@@ -92,8 +91,6 @@ struct flic_server {
     std::vector<flic_scan> scans;
     std::vector<const float*> h_in;
     std::vector<int32_t*> h_out;
-    // host ranges the runtime reported device-accessible at their own address
-    std::unordered_map<const void*, size_t> visible;
     std::vector<char> direct;              // per frame of the launch being built: passes use its host buffers
 };
 
@@ -103,11 +100,10 @@ bool device_mode(const flic_server* s) { return s->ctx != nullptr; }
 
 // Whether the device can read and write [p, p + bytes) at the same addresses
 // (pinned host memory mapped into the device's address space), both ends
-// asked of the HIP runtime; remembered per buffer.
-bool device_visible(flic_server* s, const void* p, size_t bytes) {
+// asked of the HIP runtime for every frame (an address seen before may since
+// belong to another allocation).
+bool device_visible(const void* p, size_t bytes) {
     if (!p || bytes == 0 || (reinterpret_cast<uintptr_t>(p) & 15)) return false;
-    const auto it = s->visible.find(p);
-    if (it != s->visible.end() && it->second >= bytes) return true;
     const char* ends[2] = {static_cast<const char*>(p), static_cast<const char*>(p) + bytes - 1};
     for (const char* q : ends) {
         hipPointerAttribute_t a{};
@@ -117,7 +113,6 @@ bool device_visible(flic_server* s, const void* p, size_t bytes) {
         }
         if (a.type != hipMemoryTypeHost || a.devicePointer != q) return false;
     }
-    s->visible[p] = bytes;
     return true;
 }
 
@@ -413,7 +408,7 @@ flic_status flic_server_submit(flic_server* s, double now, double t_arrival, int
     fr.t_arrival = t_arrival;
     if (device_mode(s) && s->cfg.stage_kernels) {
         const size_t bytes = (size_t)sn.H * sn.W * 4;
-        fr.staged = device_visible(s, host_range, bytes) && device_visible(s, host_labels, bytes);
+        fr.staged = device_visible(host_range, bytes) && device_visible(host_labels, bytes);
     }
     const int32_t idx = (int32_t)s->frames.size();
     s->frames.push_back(fr);
