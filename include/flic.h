@@ -295,10 +295,11 @@ flic_status flic_ground_remove(flic_ctx* ctx, const float* range_in, int32_t n_s
  * max_queue waiting frames the oldest is dropped.  It is admitted when one
  * of its sensor's slots is free.  Whenever one of n_streams launch streams
  * is idle, every admitted frame not yet launched (oldest first, at most
- * max_batch) goes out in one flic_cluster_batched_host call on that stream:
- * each frame's host-to-device copy, one batched launch, each frame's labels
- * back to its host buffer.  Labels are those of flic_cluster (scan-local
- * linear indices, Section III.B, no size threshold, dense skip edges).
+ * max_batch) goes out as one launch on that stream: each frame's range in,
+ * one flic_cluster_batched of the frames, each frame's labels back to its
+ * host buffer (how the frames move: stage_kernels, below).  Labels are those
+ * of flic_cluster (scan-local linear indices, Section III.B, no size
+ * threshold, dense skip edges).
  *
  * Times are seconds on the server's clock (flic_server_now: a monotonic clock
  * started at creation).  submit and progress take the current time from the
@@ -311,7 +312,9 @@ flic_status flic_ground_remove(flic_ctx* ctx, const float* range_in, int32_t n_s
  * directly; with 2, the clustering passes themselves read the ranges from
  * and write the labels to the host buffers.  A frame whose buffers the HIP
  * runtime does not report as device-accessible at the same address (or that
- * are not 16-byte aligned) is copied with hipMemcpyAsync instead.
+ * are not 16-byte aligned) is copied with hipMemcpyAsync instead, and so is
+ * (with 2) one whose host buffers overlap those of another frame of the
+ * same launch.
  *
  * With ctx == NULL the server simulates the device: nothing is allocated or
  * launched, and a launch is done sim_launch_s seconds after it was made
