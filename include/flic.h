@@ -312,9 +312,9 @@ flic_status flic_ground_remove(flic_ctx* ctx, const float* range_in, int32_t n_s
  * directly; with 2, the clustering passes themselves read the ranges from
  * and write the labels to the host buffers.  A frame whose buffers the HIP
  * runtime does not report as device-accessible at the same address (or that
- * are not 16-byte aligned) is copied with hipMemcpyAsync instead, and so is
- * (with 2) one whose host buffers overlap those of another frame of the
- * same launch.
+ * are not 16-byte aligned) is copied with hipMemcpyAsync instead.  With 2,
+ * a frame whose host buffers overlap those of another frame of the same
+ * launch goes through its device slot and is copied as with 1.
  *
  * With ctx == NULL the server simulates the device: nothing is allocated or
  * launched, and a launch is done sim_launch_s seconds after it was made
